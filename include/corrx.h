@@ -1,0 +1,189 @@
+/*
+ * corrx.h -- C ABI of the MI355X (gfx950) X-engine.
+ *
+ * The X-engine is the cross-multiply-accumulate stage of an FX correlator
+ * (Ord et al., "The Murchison Widefield Array Correlator", Sec. 2 eq. (3) and
+ * Sec. 3.4).  For every fine frequency channel f and every input pair
+ * 0 <= j <= i < N it forms
+ *
+ *     V_f[i][j] = sum_t x_i(f,t) * conj(x_j(f,t))
+ *
+ * from packed 4+4-bit complex samples, keeping the lower triangle of the
+ * Hermitian matrix including the autocorrelations (Appendix C, "GPU Output").
+ * All sums are exact integers: the library accumulates in int32.
+ *
+ * Conventions shared by every entry point:
+ *   - Sample byte (Appendix A, data-format list): high nibble = real part,
+ *     low nibble = imaginary part, 4-bit two's complement.  The code 8 (-8)
+ *     marks invalid data; a sample with the code in either nibble contributes
+ *     nothing (it is treated as 0 + 0j).
+ *   - Input index i = 2*station + polarisation (Appendix C, "GPU Input":
+ *     station, then polarisation, fastest last).
+ *   - Pointers named in, acc, dst, bufs are DEVICE pointers (HIP device memory,
+ *     e.g. torch tensors) owned by the caller; they must stay valid until the
+ *     work queued on `stream` has completed.  `stream` is a hipStream_t (NULL =
+ *     the null stream).  Calls enqueue work and return without synchronising;
+ *     device-side faults surface at the caller's next synchronisation.
+ *   - Every entry point returns CORRX_OK or a negative status.  Argument errors
+ *     are detected before anything is enqueued.  No C++ exception crosses the ABI.
+ *   - A handle is used by one host thread and one stream at a time.  Distinct
+ *     handles may be used concurrently on different streams.
+ */
+#ifndef CORRX_H
+#define CORRX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CORRX_ABI_VERSION 1
+
+typedef struct corrx_ctx *corrx_t;
+typedef struct corrx_batch *corrx_batch_t;
+
+/* Status codes. */
+enum {
+    CORRX_OK = 0,
+    CORRX_EINVAL = -1,       /* bad argument: null pointer, size, enum value */
+    CORRX_ENOMEM = -2,       /* host or device allocation failed */
+    CORRX_EDEVICE = -3,      /* no usable gfx950 device, or a HIP call / launch failed */
+    CORRX_EUNSUPPORTED = -4, /* valid request this build cannot serve */
+    CORRX_EOVERFLOW = -5     /* the int32 accumulator could overflow: zero it first */
+};
+
+/* Input layouts of the packed sample buffer (N*F*T bytes). */
+enum {
+    CORRX_LAYOUT_TFI = 0, /* byte (t*F + f)*N + i: the paper's GPU input order (App. C) */
+    CORRX_LAYOUT_FTI = 1  /* byte (f*T + t)*N + i: one contiguous block per channel */
+};
+
+/* Output orders of corr_dump. */
+enum {
+    /* f, then b = i*(i+1)/2 + j for i >= j, then {re, im}: N(N+1)/2 per channel. */
+    CORRX_TRI_INPUT = 0,
+    /* Appendix C "GPU Output": f, then s1 >= s2 packed as s1*(s1+1)/2 + s2, then
+     * p1, p2 in {0,1}, then {re, im}; element = V[2*s1+p1][2*s2+p2].  For s1 == s2
+     * the (p1=0, p2=1) element is conj(V[2*s1+1][2*s1]).  2N(N/2+1) per channel
+     * (33024 for N = 256, Sec. 3.4.3).  Needs an even N. */
+    CORRX_TRI_STATION_POL = 1
+};
+
+/* Element types of corr_dump (both exact at the sizes corr_dump accepts). */
+enum { CORRX_I32 = 0, CORRX_F32 = 1 };
+
+/* Compute engines.  All are bit-exact; they differ in speed only. */
+enum {
+    CORRX_ENGINE_AUTO = 0,    /* currently MFMA_I8 */
+    CORRX_ENGINE_PLAIN = 1,   /* vector ALU only (no matrix cores) */
+    CORRX_ENGINE_MFMA_I8 = 2, /* int8 MFMA, int32 accumulation */
+    CORRX_ENGINE_MFMA_F8 = 3  /* fp8 E4M3 MFMA, fp32 accumulation in exact chunks folded to int32 */
+};
+
+/* Library version, for checking the binding against the header. */
+int corr_abi_version(void);
+
+/* Human-readable text of a status code (static storage, never NULL). */
+const char *corr_strerror(int status);
+
+/*
+ * Create a correlator for n_inputs inputs, n_chan fine channels and n_time
+ * samples per corr_xmac call, with the given input layout (Sec. 1.1: the
+ * problem is fixed by the number of inputs, channels and the integration).
+ * Selects the current HIP device, which must be gfx950; allocates only the
+ * host-side handle.  Sizes: 1 <= n_inputs <= 4096, n_chan >= 1, n_time >= 1,
+ * N*F*T < 2^40.  Errors: CORRX_EINVAL, CORRX_EDEVICE (no gfx950 device),
+ * CORRX_ENOMEM.  On error *out is set to NULL.
+ */
+int corr_create(int n_inputs, int n_chan, int n_time, int layout, corrx_t *out);
+
+/* Free the handle (NULL is accepted).  Does not touch caller memory. */
+int corr_destroy(corrx_t h);
+
+/* Choose the compute engine (CORRX_ENGINE_*); default AUTO. */
+int corr_set_engine(corrx_t h, int engine);
+/* Engine that corr_xmac will run (AUTO resolved), or a negative status. */
+int corr_get_engine(corrx_t h);
+
+/* Bytes of the accumulator: n_chan * N(N+1)/2 * 2 * 4 (int32 re, im). */
+size_t corr_acc_bytes(corrx_t h);
+/* Elements (re and im counted separately) of a corr_dump in `order`, or 0 if
+ * the order is invalid for this handle. */
+size_t corr_dump_count(corrx_t h, int order);
+
+/*
+ * Set the accumulator to zero (start of an integration, Sec. 3.4.3: the
+ * accumulation length is chosen by the operator).  acc: device, corr_acc_bytes.
+ */
+int corr_zero(corrx_t h, void *acc, void *stream);
+
+/*
+ * acc += V(in): cross-multiply all input pairs of every channel over the
+ * handle's n_time samples and add the lower triangle into acc (Sec. 3.4:
+ * products are accumulated on the device).
+ *   in:  device, N*F*T bytes in the handle's layout.
+ *   acc: device, corr_acc_bytes(h) bytes, int32 [f][b][re, im], b = i(i+1)/2 + j.
+ * The handle counts samples since the last corr_zero on the host; a call that
+ * could overflow int32 (more than 21,913,098 samples, |Re|,|Im| <= 98 per
+ * sample) returns CORRX_EOVERFLOW and enqueues nothing.
+ */
+int corr_xmac(corrx_t h, const void *in, void *acc, void *stream);
+
+/*
+ * Write the visibilities in acc to dst in `order` (CORRX_TRI_*) as `dtype`
+ * (CORRX_I32 / CORRX_F32), Appendix C "GPU Output".  dst: device,
+ * corr_dump_count(h, order) * 4 bytes; must not overlap acc.  CORRX_F32 is
+ * exact while |values| <= 2^24, which holds for integrations of up to 171,196
+ * samples; past that it returns CORRX_EOVERFLOW.
+ */
+int corr_dump(corrx_t h, const void *acc, int order, int dtype, void *dst, void *stream);
+
+/* Samples accumulated since the last corr_zero (host-side count). */
+int64_t corr_samples(corrx_t h);
+
+/*
+ * Incoherent beam (Sec. 3.4, other XMAC modes): out[f][t] = sum_i |x_i(f,t)|^2
+ * as int32 for the handle's shape.  in: device, as for corr_xmac; out: device,
+ * n_chan * n_time * 4 bytes.
+ */
+int corr_beam(corrx_t h, const void *in, void *out, void *stream);
+
+/* ---- Uneven batch in one persistent launch ---------------------------- */
+
+/* One array of a batch: its own shape and input layout. */
+typedef struct {
+    int n_inputs;
+    int n_chan;
+    int n_time;
+    int layout;
+} corrx_desc;
+
+/*
+ * Plan a batch of n arrays (1 <= n <= 64) of uneven shapes, run by one
+ * persistent launch that pulls work items (array, channel, tile, time range)
+ * from a device queue.  engine: CORRX_ENGINE_MFMA_I8 or AUTO.  Allocates the
+ * device work list and queue counter (freed by corr_batch_destroy).
+ * tile_cfg: per-array tile-shape code from the autotuner (NULL = built-in
+ * choice); each code is a CORRX_TILE_* value.
+ */
+enum { CORRX_TILE_DEFAULT = 0, CORRX_TILE_T64 = 1, CORRX_TILE_T32 = 2 };
+int corr_batch_create(const corrx_desc *descs, int n, int engine, const int *tile_cfg,
+                      corrx_batch_t *out);
+int corr_batch_destroy(corrx_batch_t b);
+
+/* Work items in the plan (for reporting). */
+int64_t corr_batch_items(corrx_batch_t b);
+
+/*
+ * For every array a: accs[a] += V(ins[a]).  ins and accs are HOST arrays of n
+ * DEVICE pointers (same meaning as for corr_xmac, one per array).  One launch.
+ */
+int corr_batch_xmac(corrx_batch_t b, const void *const *ins, void *const *accs, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORRX_H */

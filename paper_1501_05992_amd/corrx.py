@@ -1,0 +1,261 @@
+"""ctypes binding of libcorrx.so (include/corrx.h), same names as the C ABI.
+
+Argument marshalling only: every step of the correlation runs in the HIP
+library.  PyTorch supplies device memory and streams; it is imported before
+the library is loaded so that both use the one HIP runtime PyTorch brought
+into the process.  There is no fallback: without the built library on a
+gfx950 device every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime first; see module docstring)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcorrx.so")
+
+CORRX_OK = 0
+CORRX_EINVAL = -1
+CORRX_ENOMEM = -2
+CORRX_EDEVICE = -3
+CORRX_EUNSUPPORTED = -4
+CORRX_EOVERFLOW = -5
+
+CORRX_LAYOUT_TFI = 0
+CORRX_LAYOUT_FTI = 1
+CORRX_TRI_INPUT = 0
+CORRX_TRI_STATION_POL = 1
+CORRX_I32 = 0
+CORRX_F32 = 1
+CORRX_ENGINE_AUTO = 0
+CORRX_ENGINE_PLAIN = 1
+CORRX_ENGINE_MFMA_I8 = 2
+CORRX_ENGINE_MFMA_F8 = 3
+CORRX_TILE_DEFAULT = 0
+CORRX_TILE_T64 = 1
+CORRX_TILE_T32 = 2
+
+ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
+           "mfma_i8": CORRX_ENGINE_MFMA_I8, "mfma_f8": CORRX_ENGINE_MFMA_F8}
+
+# Exported symbols, in header order.
+SYMBOLS = ("corr_abi_version", "corr_strerror", "corr_create", "corr_destroy", "corr_set_engine",
+           "corr_get_engine", "corr_acc_bytes", "corr_dump_count", "corr_zero", "corr_xmac",
+           "corr_dump", "corr_samples", "corr_beam", "corr_batch_create", "corr_batch_destroy",
+           "corr_batch_items", "corr_batch_xmac")
+
+
+class CorrxError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {corr_strerror(status)} ({status})")
+
+
+class corrx_desc(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int), ("n_chan", ctypes.c_int),
+                ("n_time", ctypes.c_int), ("layout", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcorrx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1501_05992_amd.build` or __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, sz, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_int64
+        sig = {
+            "corr_abi_version": ([], i),
+            "corr_strerror": ([i], ctypes.c_char_p),
+            "corr_create": ([i, i, i, i, ctypes.POINTER(vp)], i),
+            "corr_destroy": ([vp], i),
+            "corr_set_engine": ([vp, i], i),
+            "corr_get_engine": ([vp], i),
+            "corr_acc_bytes": ([vp], sz),
+            "corr_dump_count": ([vp, i], sz),
+            "corr_zero": ([vp, vp, vp], i),
+            "corr_xmac": ([vp, vp, vp, vp], i),
+            "corr_dump": ([vp, vp, i, i, vp, vp], i),
+            "corr_samples": ([vp], i64),
+            "corr_beam": ([vp, vp, vp, vp], i),
+            "corr_batch_create": ([ctypes.POINTER(corrx_desc), i, i, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(vp)], i),
+            "corr_batch_destroy": ([vp], i),
+            "corr_batch_items": ([vp], i64),
+            "corr_batch_xmac": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp], i),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        if L.corr_abi_version() != 1:
+            raise RuntimeError("libcorrx.so ABI version does not match the binding")
+        _lib = L
+    return _lib
+
+
+def corr_strerror(status: int) -> str:
+    return lib().corr_strerror(int(status)).decode()
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise CorrxError(rc, what)
+    return rc
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---- flat C-ABI names ---------------------------------------------------------
+
+def corr_create(n_inputs: int, n_chan: int, n_time: int, layout: int = CORRX_LAYOUT_TFI) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().corr_create(n_inputs, n_chan, n_time, layout, ctypes.byref(h)), "corr_create")
+    return h.value
+
+
+def corr_destroy(h: int) -> None:
+    _check(lib().corr_destroy(h), "corr_destroy")
+
+
+def corr_set_engine(h: int, engine: int) -> None:
+    _check(lib().corr_set_engine(h, engine), "corr_set_engine")
+
+
+def corr_get_engine(h: int) -> int:
+    return _check(lib().corr_get_engine(h), "corr_get_engine")
+
+
+def corr_acc_bytes(h: int) -> int:
+    return int(lib().corr_acc_bytes(h))
+
+
+def corr_dump_count(h: int, order: int) -> int:
+    return int(lib().corr_dump_count(h, order))
+
+
+def corr_samples(h: int) -> int:
+    return int(lib().corr_samples(h))
+
+
+def corr_zero(h: int, acc, stream=None) -> None:
+    _check(lib().corr_zero(h, _ptr(acc), _stream(stream)), "corr_zero")
+
+
+def corr_xmac(h: int, inp, acc, stream=None) -> None:
+    _check(lib().corr_xmac(h, _ptr(inp), _ptr(acc), _stream(stream)), "corr_xmac")
+
+
+def corr_dump(h: int, acc, order: int, dtype: int, dst, stream=None) -> None:
+    _check(lib().corr_dump(h, _ptr(acc), order, dtype, _ptr(dst), _stream(stream)), "corr_dump")
+
+
+def corr_beam(h: int, inp, out, stream=None) -> None:
+    _check(lib().corr_beam(h, _ptr(inp), _ptr(out), _stream(stream)), "corr_beam")
+
+
+def corr_batch_create(descs, engine: int = CORRX_ENGINE_AUTO, tile_cfg=None) -> int:
+    n = len(descs)
+    arr = (corrx_desc * n)(*[corrx_desc(*d) for d in descs])
+    cfg = None
+    if tile_cfg is not None:
+        cfg = (ctypes.c_int * n)(*[int(c) for c in tile_cfg])
+    h = ctypes.c_void_p()
+    _check(lib().corr_batch_create(arr, n, engine, cfg, ctypes.byref(h)), "corr_batch_create")
+    return h.value
+
+
+def corr_batch_destroy(b: int) -> None:
+    _check(lib().corr_batch_destroy(b), "corr_batch_destroy")
+
+
+def corr_batch_items(b: int) -> int:
+    return int(_check(lib().corr_batch_items(b), "corr_batch_items"))
+
+
+def corr_batch_xmac(b: int, ins, accs, stream=None) -> None:
+    n = len(ins)
+    pin = (ctypes.c_void_p * n)(*[_ptr(x) for x in ins])
+    pacc = (ctypes.c_void_p * n)(*[_ptr(x) for x in accs])
+    _check(lib().corr_batch_xmac(b, pin, pacc, _stream(stream)), "corr_batch_xmac")
+
+
+# ---- convenience wrapper --------------------------------------------------------
+
+class Correlator:
+    """One correlator handle: shape fixed at creation (corr_create)."""
+
+    def __init__(self, n_inputs: int, n_chan: int, n_time: int, layout: int = CORRX_LAYOUT_TFI,
+                 engine: int | str = CORRX_ENGINE_AUTO):
+        self.n_inputs, self.n_chan, self.n_time, self.layout = n_inputs, n_chan, n_time, layout
+        self.h = corr_create(n_inputs, n_chan, n_time, layout)
+        if isinstance(engine, str):
+            engine = ENGINES[engine]
+        corr_set_engine(self.h, engine)
+
+    def close(self) -> None:
+        if self.h:
+            corr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def engine(self) -> int:
+        return corr_get_engine(self.h)
+
+    def set_engine(self, engine: int | str) -> None:
+        corr_set_engine(self.h, ENGINES[engine] if isinstance(engine, str) else engine)
+
+    def new_acc(self, device="cuda") -> torch.Tensor:
+        nb = self.n_inputs * (self.n_inputs + 1) // 2
+        return torch.zeros((self.n_chan, nb, 2), dtype=torch.int32, device=device)
+
+    def zero(self, acc, stream=None) -> None:
+        corr_zero(self.h, acc, stream)
+
+    def xmac(self, inp, acc, stream=None) -> None:
+        corr_xmac(self.h, inp, acc, stream)
+
+    def dump(self, acc, order: int = CORRX_TRI_INPUT, dtype: int = CORRX_I32, dst=None, stream=None):
+        n = corr_dump_count(self.h, order)
+        if dst is None:
+            dst = torch.empty(n, dtype=torch.int32 if dtype == CORRX_I32 else torch.float32,
+                              device=acc.device)
+        corr_dump(self.h, acc, order, dtype, dst, stream)
+        return dst
+
+    def beam(self, inp, out=None, stream=None):
+        if out is None:
+            out = torch.empty((self.n_chan, self.n_time), dtype=torch.int32, device=inp.device)
+        corr_beam(self.h, inp, out, stream)
+        return out
+
+    @property
+    def samples(self) -> int:
+        return corr_samples(self.h)

@@ -1,0 +1,178 @@
+// api.hip -- the C ABI of include/corrx.h: argument validation, device check,
+// engine dispatch, time-split planning.  No C++ exception crosses the ABI.
+
+#include <string.h>
+
+#include <new>
+
+#include "corrx_internal.h"
+
+using namespace corrx;
+
+struct corrx_ctx {
+  int n_inputs, n_chan, n_time, layout;
+  int engine;      // requested (may be AUTO)
+  int device;
+  int n_cu;
+  int64_t samples; // since the last corr_zero
+};
+
+namespace {
+
+bool device_ok(int* dev, int* n_cu) {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return false;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, d) != hipSuccess) return false;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return false;
+  *dev = d;
+  *n_cu = prop.multiProcessorCount;
+  return true;
+}
+
+int resolve_engine(int e) { return e == CORRX_ENGINE_AUTO ? CORRX_ENGINE_MFMA_I8 : e; }
+
+// Time splits per channel: enough work units to fill the chip (about two per
+// compute unit), at least 512 samples per split, at most kMaxUnitTime.
+int plan_splits(int n_chan, int units_per_chan, int n_time, int n_cu) {
+  const int64_t units = (int64_t)n_chan * units_per_chan;
+  int split = 1;
+  const int64_t target = 2LL * n_cu;
+  while (units * split < target && n_time / (2 * split) >= 512) split *= 2;
+  while ((n_time + split - 1) / split > kMaxUnitTime) ++split;
+  return split;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+int corr_abi_version(void) { return CORRX_ABI_VERSION; }
+
+const char* corr_strerror(int status) {
+  switch (status) {
+    case CORRX_OK: return "ok";
+    case CORRX_EINVAL: return "invalid argument";
+    case CORRX_ENOMEM: return "out of memory";
+    case CORRX_EDEVICE: return "no usable gfx950 device or a HIP call failed";
+    case CORRX_EUNSUPPORTED: return "unsupported request";
+    case CORRX_EOVERFLOW: return "int32 accumulator could overflow";
+    default: return "unknown status";
+  }
+}
+
+int corr_create(int n_inputs, int n_chan, int n_time, int layout, corrx_t* out) {
+  if (!out) return CORRX_EINVAL;
+  *out = nullptr;
+  if (n_inputs < 1 || n_inputs > 4096 || n_chan < 1 || n_time < 1) return CORRX_EINVAL;
+  if (layout != CORRX_LAYOUT_TFI && layout != CORRX_LAYOUT_FTI) return CORRX_EINVAL;
+  const double bytes = (double)n_inputs * n_chan * n_time;
+  if (bytes >= 1099511627776.0) return CORRX_EINVAL;
+  int dev = 0, n_cu = 0;
+  if (!device_ok(&dev, &n_cu)) return CORRX_EDEVICE;
+  corrx_ctx* h = new (std::nothrow) corrx_ctx;
+  if (!h) return CORRX_ENOMEM;
+  h->n_inputs = n_inputs;
+  h->n_chan = n_chan;
+  h->n_time = n_time;
+  h->layout = layout;
+  h->engine = CORRX_ENGINE_AUTO;
+  h->device = dev;
+  h->n_cu = n_cu;
+  h->samples = 0;
+  *out = h;
+  return CORRX_OK;
+}
+
+int corr_destroy(corrx_t h) {
+  delete h;
+  return CORRX_OK;
+}
+
+int corr_set_engine(corrx_t h, int engine) {
+  if (!h) return CORRX_EINVAL;
+  if (engine < CORRX_ENGINE_AUTO || engine > CORRX_ENGINE_MFMA_F8) return CORRX_EINVAL;
+  h->engine = engine;
+  return CORRX_OK;
+}
+
+int corr_get_engine(corrx_t h) {
+  if (!h) return CORRX_EINVAL;
+  return resolve_engine(h->engine);
+}
+
+size_t corr_acc_bytes(corrx_t h) {
+  if (!h) return 0;
+  return (size_t)h->n_chan * (size_t)tri_index(h->n_inputs, 0) * 2 * sizeof(int);
+}
+
+size_t corr_dump_count(corrx_t h, int order) {
+  if (!h) return 0;
+  if (order == CORRX_TRI_INPUT) return (size_t)h->n_chan * (size_t)tri_index(h->n_inputs, 0) * 2;
+  if (order == CORRX_TRI_STATION_POL) {
+    if (h->n_inputs % 2) return 0;
+    return (size_t)h->n_chan * (size_t)tri_index(h->n_inputs / 2, 0) * 8;
+  }
+  return 0;
+}
+
+int64_t corr_samples(corrx_t h) { return h ? h->samples : CORRX_EINVAL; }
+
+int corr_zero(corrx_t h, void* acc, void* stream) {
+  if (!h || !acc) return CORRX_EINVAL;
+  const int rc = launch_zero(static_cast<int*>(acc), (int64_t)(corr_acc_bytes(h) / sizeof(int)), as_stream(stream));
+  if (rc == CORRX_OK) h->samples = 0;
+  return rc;
+}
+
+int corr_xmac(corrx_t h, const void* in, void* acc, void* stream) {
+  if (!h || !in || !acc) return CORRX_EINVAL;
+  if (h->samples + h->n_time > kMaxAccSamples) return CORRX_EOVERFLOW;
+  Problem p;
+  p.in = static_cast<const uint8_t*>(in);
+  p.acc = static_cast<int*>(acc);
+  p.n_inputs = h->n_inputs;
+  p.n_chan = h->n_chan;
+  p.n_time = h->n_time;
+  p.layout = h->layout;
+  const int engine = resolve_engine(h->engine);
+  int rc;
+  if (engine == CORRX_ENGINE_PLAIN) {
+    const int nbk = (h->n_inputs + 63) / 64;
+    rc = launch_plain(p, plan_splits(h->n_chan, nbk * (nbk + 1) / 2, h->n_time, h->n_cu), as_stream(stream));
+  } else {
+    rc = launch_mfma(p, engine, plan_splits(h->n_chan, 1, h->n_time, h->n_cu), CORRX_TILE_DEFAULT,
+                     as_stream(stream));
+  }
+  if (rc == CORRX_OK) h->samples += h->n_time;
+  return rc;
+}
+
+int corr_dump(corrx_t h, const void* acc, int order, int dtype, void* dst, void* stream) {
+  if (!h || !acc || !dst) return CORRX_EINVAL;
+  if (order != CORRX_TRI_INPUT && order != CORRX_TRI_STATION_POL) return CORRX_EINVAL;
+  if (dtype != CORRX_I32 && dtype != CORRX_F32) return CORRX_EINVAL;
+  if (order == CORRX_TRI_STATION_POL && h->n_inputs % 2) return CORRX_EINVAL;
+  if (dtype == CORRX_F32 && h->samples > kMaxF32Samples) return CORRX_EOVERFLOW;
+  const char* a = static_cast<const char*>(acc);
+  const char* d = static_cast<const char*>(dst);
+  const size_t na = corr_acc_bytes(h), nd = corr_dump_count(h, order) * 4;
+  if (a < d + nd && d < a + na) return CORRX_EINVAL;
+  return launch_dump(static_cast<const int*>(acc), h->n_inputs, h->n_chan, order, dtype, dst, as_stream(stream));
+}
+
+int corr_beam(corrx_t h, const void* in, void* out, void* stream) {
+  if (!h || !in || !out) return CORRX_EINVAL;
+  Problem p;
+  p.in = static_cast<const uint8_t*>(in);
+  p.acc = nullptr;
+  p.n_inputs = h->n_inputs;
+  p.n_chan = h->n_chan;
+  p.n_time = h->n_time;
+  p.layout = h->layout;
+  return launch_beam(p, static_cast<int*>(out), as_stream(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// corrx_internal.h -- shared definitions of the gfx950 X-engine kernels and
+// the host library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/corrx.h"
+
+namespace corrx {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Largest time range one work unit integrates.  Bounds the biased int32 sums
+// of the MFMA engines (|G_b| <= 900 per sample) well inside int32.
+constexpr int kMaxUnitTime = 1 << 20;
+
+// int32 bound of the accumulator: |Re|, |Im| <= 2 * 7 * 7 = 98 per sample.
+constexpr int64_t kMaxAccSamples = 21913098;  // floor((2^31 - 1) / 98)
+// float32 exactness of a dump: |value| <= 2^24.
+constexpr int64_t kMaxF32Samples = 171196;    // floor(2^24 / 98)
+
+// Description of one correlation problem as seen by a kernel.
+struct Problem {
+  const uint8_t* in;   // packed samples
+  int* acc;            // int32 [f][b][2]
+  int n_inputs;
+  int n_chan;
+  int n_time;
+  int layout;          // CORRX_LAYOUT_*
+};
+
+__host__ __device__ inline int64_t row_offset(const Problem& p, int f, int t) {
+  return p.layout == CORRX_LAYOUT_TFI ? ((int64_t)t * p.n_chan + f) * p.n_inputs
+                                      : ((int64_t)f * p.n_time + t) * p.n_inputs;
+}
+
+__host__ __device__ inline int64_t tri_index(int i, int j) {
+  return (int64_t)i * (i + 1) / 2 + j;
+}
+
+// ---- packed-sample helpers (device) ---------------------------------------
+
+// 4x4 byte transpose: d_r holds byte c = sample (time r, input c); the result
+// e_c holds byte r = sample (time r, input c).  v_perm_b32 picks bytes of
+// {S0:S1}, selector values 0-3 from S1 and 4-7 from S0.
+__device__ inline void transpose4x4(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3,
+                                    uint32_t& e0, uint32_t& e1, uint32_t& e2, uint32_t& e3) {
+  const uint32_t t01l = __builtin_amdgcn_perm(d1, d0, 0x05010400u);
+  const uint32_t t01h = __builtin_amdgcn_perm(d1, d0, 0x07030602u);
+  const uint32_t t23l = __builtin_amdgcn_perm(d3, d2, 0x05010400u);
+  const uint32_t t23h = __builtin_amdgcn_perm(d3, d2, 0x07030602u);
+  e0 = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u);
+  e1 = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u);
+  e2 = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u);
+  e3 = __builtin_amdgcn_perm(t23h, t01h, 0x07060302u);
+}
+
+// Bias four packed samples: y = x ^ 0x88 per byte, so that each nibble holds
+// its 4-bit two's complement value plus 8 (range 0..15).  A nibble of 0 in y is
+// the invalid code.
+__device__ inline uint32_t bias4(uint32_t x) { return x ^ 0x88888888u; }
+
+// Nonzero (in bits 3 and 7 of some byte) iff some nibble of y is zero, i.e.
+// some sample of the four is invalid.  Exact as an "any" test.
+__device__ inline uint32_t invalid_flags(uint32_t y) {
+  return (y - 0x11111111u) & ~y & 0x88888888u;
+}
+
+// Replace every byte of y that has a zero nibble by 0x88 (a valid 0 + 0j):
+// an invalid sample contributes nothing.
+__device__ inline uint32_t mask_invalid(uint32_t y) {
+  const uint32_t nz = (((y & 0x77777777u) + 0x77777777u) | y) & 0x88888888u;  // bit 3 per nonzero nibble
+  const uint32_t both = nz & (nz >> 4) & 0x08080808u;                          // bit 3 per valid byte
+  const uint32_t one = both >> 3;                                              // 0x01 per valid byte
+  const uint32_t m = (one << 8) - one;                                         // 0xFF per valid byte
+  return (y & m) | (0x88888888u & ~m);
+}
+
+// Biased real / imaginary parts (0..15) of four samples, one per byte.
+__device__ inline uint32_t bre4(uint32_t y) { return (y >> 4) & 0x0F0F0F0Fu; }
+__device__ inline uint32_t bim4(uint32_t y) { return y & 0x0F0F0F0Fu; }
+
+// Second GEMM operand from the first, for four samples per dword:
+//   s = (re+8) + (im+8)      = re + im + 16   in 0..30
+//   d = (im+8) - (re+8) + 15 = im - re + 15   in 0..30
+// Bytes never carry or borrow into each other.
+__device__ inline uint32_t op_s(uint32_t r, uint32_t i) { return r + i; }
+__device__ inline uint32_t op_d(uint32_t r, uint32_t i) { return (i + 0x0F0F0F0Fu) - r; }
+
+// Sum of the four bytes of x, added to acc.
+__device__ inline uint32_t bytesum(uint32_t x, uint32_t acc) {
+  return __builtin_amdgcn_udot4(x, 0x01010101u, acc, false);
+}
+
+// ---- launchers (defined in the kernel translation units) ------------------
+
+struct LaunchStatus {
+  int status;
+};
+
+// int8 / fp8 MFMA engine over one problem.  nsplit: time splits per channel
+// (each at most kMaxUnitTime samples); atomic accumulation when nsplit > 1.
+int launch_mfma(const Problem& p, int engine, int nsplit, int tile_cfg, hipStream_t s);
+// vector-ALU engine.
+int launch_plain(const Problem& p, int nsplit, hipStream_t s);
+// accumulator fill, dump and incoherent beam.
+int launch_zero(int* acc, int64_t n_words, hipStream_t s);
+int launch_dump(const int* acc, int n_inputs, int n_chan, int order, int dtype, void* dst, hipStream_t s);
+int launch_beam(const Problem& p, int* out, hipStream_t s);
+
+// ---- persistent batched engine ---------------------------------------------
+
+// One work item of the persistent kernel.
+struct WorkItem {
+  int array;     // index into the batch's problem table
+  int channel;
+  int tile;      // unit index within the channel (see unit decoding in the kernel)
+  int t0;        // first sample
+  int t1;        // one past the last sample
+  int kind;      // unit kind and shape code
+};
+
+struct BatchArray {
+  Problem p;
+  int nsplit;     // time splits per (channel, tile)
+  int units;      // units per channel
+  int unit_kind;  // shape code of this array's units
+};
+
+int launch_batch(const BatchArray* d_arrays, const WorkItem* d_items, int64_t n_items, int* d_counter,
+                 int grid, hipStream_t s);
+int batch_max_grid();
+
+}  // namespace corrx

@@ -1,0 +1,78 @@
+"""C-ABI library checks that need no GPU: it loads, exports every symbol that
+include/corrx.h declares, and rejects bad arguments / a missing device cleanly.
+No compute call is made here."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "corrx.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(corr_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def cx():
+    from paper_1501_05992_amd import corrx
+
+    if not os.path.exists(corrx.LIB_PATH):
+        from paper_1501_05992_amd import build
+
+        build.build()
+    return corrx
+
+
+def test_header_declares_the_binding_symbols(cx):
+    assert _declared() == sorted(cx.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(cx):
+    L = cx.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert L.corr_abi_version() == 1
+
+
+def test_strerror(cx):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert cx.corr_strerror(code)
+    assert cx.corr_strerror(-99) == "unknown status"
+
+
+def test_create_rejects_bad_arguments_before_touching_the_device(cx):
+    L = cx.lib()
+    h = ctypes.c_void_p(123)
+    for args in [(0, 1, 1, 0), (5000, 1, 1, 0), (4, 0, 1, 0), (4, 1, 0, 0), (4, 1, 1, 7),
+                 (4096, 65536, 65536, 0)]:
+        assert L.corr_create(*args, ctypes.byref(h)) == cx.CORRX_EINVAL
+        assert h.value is None
+    assert L.corr_create(4, 1, 1, 0, None) == cx.CORRX_EINVAL
+
+
+def test_null_handle_calls(cx):
+    L = cx.lib()
+    assert L.corr_xmac(None, None, None, None) == cx.CORRX_EINVAL
+    assert L.corr_zero(None, None, None) == cx.CORRX_EINVAL
+    assert L.corr_dump(None, None, 0, 0, None, None) == cx.CORRX_EINVAL
+    assert L.corr_set_engine(None, 0) == cx.CORRX_EINVAL
+    assert L.corr_acc_bytes(None) == 0
+    assert L.corr_destroy(None) == cx.CORRX_OK
+    assert L.corr_batch_xmac(None, None, None, None) in (cx.CORRX_EINVAL, cx.CORRX_EUNSUPPORTED)
+
+
+def test_no_gpu_means_edevice(cx):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert cx.lib().corr_create(256, 8, 2000, 0, ctypes.byref(h)) == cx.CORRX_EDEVICE
+    with pytest.raises(cx.CorrxError):
+        cx.corr_create(256, 8, 2000)

@@ -1,0 +1,185 @@
+"""GPU parity: every engine of the C-ABI library against the CPU oracle,
+element by element, tolerance 0 (all sums are exact integers)."""
+
+import numpy as np
+import pytest
+
+from paper_1501_05992_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ENGINES = ["plain", "mfma_i8"]
+
+
+@pytest.fixture(scope="module")
+def cx():
+    import torch
+
+    from paper_1501_05992_amd import corrx
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    corrx.lib()
+    return corrx
+
+
+def _run(cx, buf, n, fc, tc, layout=0, engine="mfma_i8", calls=1):
+    import torch
+
+    dev = torch.device("cuda:0")
+    c = cx.Correlator(n, fc, tc, layout, engine)
+    x = torch.from_numpy(np.ascontiguousarray(buf)).to(dev)
+    acc = c.new_acc(dev)
+    c.zero(acc)
+    for _ in range(calls):
+        c.xmac(x, acc)
+    torch.cuda.synchronize()
+    out = acc.cpu().numpy().astype(np.int64)
+    c.close()
+    return out
+
+
+def _compare(got, want, n, label):
+    if np.array_equal(got, want):
+        return
+    bad = np.argwhere(got != want)
+    f, b, part = bad[0]
+    i = int((np.sqrt(8 * b + 1) - 1) // 2)
+    j = b - i * (i + 1) // 2
+    raise AssertionError(f"{label}: {len(bad)} mismatches; first f={f} (i={i}, j={j}) part={part} "
+                         f"got {got[f, b, part]} want {want[f, b, part]}")
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_config_plain_tiny(cx, oracle_lib, engine):
+    # 256 inputs, 8 channels, 2000 samples (the small configuration)
+    n, fc, tc = 256, 8, 2000
+    buf = synth.make_input(synth.config_seed(0), n, fc, tc)
+    _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, engine)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256])
+def test_input_counts(cx, oracle_lib, engine, n):
+    fc, tc = 3, 97
+    buf = synth.make_input(1000 + n, n, fc, tc)
+    _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} N={n}")
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("tc", [1, 15, 16, 63, 64, 65, 129, 1000, 4097])
+def test_ragged_time(cx, oracle_lib, engine, tc):
+    n, fc = 256, 2
+    buf = synth.make_input(2000 + tc, n, fc, tc)
+    _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} T={tc}")
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("layout", [0, 1])
+def test_layouts(cx, oracle_lib, engine, layout):
+    n, fc, tc = 96, 5, 333
+    buf = synth.make_input(3000, n, fc, tc, layout=layout)
+    _compare(_run(cx, buf, n, fc, tc, layout, engine), oracle_lib.xmac(buf, n, fc, tc, layout), n,
+             f"{engine} layout={layout}")
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n", [7, 128, 256])
+def test_invalid_codes_and_extreme_values(cx, oracle_lib, engine, n):
+    # every byte value occurs, including the invalid code in either nibble,
+    # and long runs of the extreme samples (+-7 +-7j)
+    fc, tc = 2, 300
+    rng = np.random.default_rng(n)
+    buf = rng.integers(0, 256, size=n * fc * tc, dtype=np.uint8)
+    buf[: n * 40] = 0x77
+    buf[n * 40: n * 80] = 0x99
+    buf[n * 80: n * 90] = 0x79
+    _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} bytes")
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_accumulates_across_calls(cx, oracle_lib, engine):
+    n, fc, tc = 64, 4, 200
+    buf = synth.make_input(4000, n, fc, tc)
+    _compare(_run(cx, buf, n, fc, tc, engine=engine, calls=3), 3 * oracle_lib.xmac(buf, n, fc, tc), n,
+             f"{engine} x3")
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_time_split_path(cx, oracle_lib, engine):
+    # few channels and many samples: the library splits time across workgroups
+    n, fc, tc = 256, 1, 20000
+    buf = synth.make_input(5000, n, fc, tc)
+    _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} split")
+
+
+def test_single_tone_closed_form(cx):
+    n, fc, tc = 256, 2, 1000
+    rng = np.random.default_rng(9)
+    gr = rng.integers(-7, 8, size=n)
+    gi = rng.integers(-7, 8, size=n)
+    buf = synth.tone_input(gr, gi, fc, tc)
+    got = _run(cx, buf, n, fc, tc)
+    g = gr + 1j * gi
+    ii, jj = np.tril_indices(n)
+    want = tc * g[ii] * np.conj(g[jj])
+    for f in range(fc):
+        assert np.array_equal(got[f, :, 0], np.rint(want.real).astype(np.int64))
+        assert np.array_equal(got[f, :, 1], np.rint(want.imag).astype(np.int64))
+
+
+def test_dump_orders_and_types(cx, oracle_lib):
+    import torch
+
+    n, fc, tc = 64, 3, 150
+    buf = synth.make_input(6000, n, fc, tc)
+    want = oracle_lib.xmac(buf, n, fc, tc)
+    c = cx.Correlator(n, fc, tc)
+    x = torch.from_numpy(buf).cuda()
+    acc = c.new_acc()
+    c.zero(acc)
+    c.xmac(x, acc)
+    tri_i = c.dump(acc, cx.CORRX_TRI_INPUT, cx.CORRX_I32).cpu().numpy()
+    tri_f = c.dump(acc, cx.CORRX_TRI_INPUT, cx.CORRX_F32).cpu().numpy()
+    sp_i = c.dump(acc, cx.CORRX_TRI_STATION_POL, cx.CORRX_I32).cpu().numpy()
+    sp_f = c.dump(acc, cx.CORRX_TRI_STATION_POL, cx.CORRX_F32).cpu().numpy()
+    assert np.array_equal(tri_i.reshape(want.shape), want)
+    assert np.array_equal(tri_f.reshape(want.shape), want.astype(np.float32))
+    sp = oracle_lib.station_pol(want, n)
+    assert sp_i.size == fc * (n // 2) * (n // 2 + 1) // 2 * 8
+    assert np.array_equal(sp_i.reshape(sp.shape), sp)
+    assert np.array_equal(sp_f.reshape(sp.shape), sp.astype(np.float32))
+    c.close()
+
+
+def test_zero_resets_and_overflow_guard(cx):
+    import torch
+
+    c = cx.Correlator(8, 1, 5_000_000)
+    x = torch.zeros(8 * 5_000_000, dtype=torch.uint8, device="cuda")
+    acc = c.new_acc()
+    c.zero(acc)
+    for _ in range(4):
+        c.xmac(x, acc)
+    with pytest.raises(cx.CorrxError) as e:
+        c.xmac(x, acc)
+    assert e.value.status == cx.CORRX_EOVERFLOW
+    with pytest.raises(cx.CorrxError):
+        c.dump(acc, cx.CORRX_TRI_INPUT, cx.CORRX_F32)
+    c.zero(acc)
+    assert c.samples == 0
+    c.xmac(x, acc)
+    torch.cuda.synchronize()
+    assert int(acc.abs().sum()) == 0
+    c.close()
+
+
+def test_beam(cx, oracle_lib):
+    import torch
+
+    n, fc, tc = 256, 4, 500
+    buf = synth.make_input(7000, n, fc, tc)
+    buf[:100] = 0x88
+    c = cx.Correlator(n, fc, tc)
+    out = c.beam(torch.from_numpy(buf).cuda()).cpu().numpy()
+    assert np.array_equal(out.astype(np.int64), oracle_lib.incoherent_beam(buf, n, fc, tc))
+    c.close()
