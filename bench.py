@@ -1,0 +1,229 @@
+"""Benchmark of the X-engine on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the full MWA band, 256 inputs (128 dual-polarisation tiles) x 3072
+fine channels x 10000 samples (1 s of data at 10 kHz), seeded synthetic
+4+4-bit samples, TFI layout, resident in HBM before timing.  One step is the
+whole hot path: corr_zero -> corr_xmac (decode + cross-multiply + integrate)
+-> corr_dump to the paper's output format (station/polarisation order, complex
+float32, Appendix C).  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_INT8_TOPS = 5000.0   # MI355X dense int8 MFMA, published
+PEAK_FP8_TFLOPS = 5000.0  # MI355X dense fp8 MFMA, published
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--engine", default="mfma_i8")
+    ap.add_argument("--n-inputs", type=int, default=256)
+    ap.add_argument("--n-chan", type=int, default=3072)
+    ap.add_argument("--n-time", type=int, default=10000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the plain-engine and small-config lines")
+    ap.add_argument("--cpu-channels", type=int, default=256, help="channels in the oracle's timed sample")
+    ap.add_argument("--check-channels", type=int, default=2, help="channels checked against the oracle")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the X-engine shards by "
+              "channel with no exchange, so N GPUs would each run this same per-GPU workload.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1501_05992_amd import corrx, model, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n, fc, tc = args.n_inputs, args.n_chan, args.n_time
+    seed = synth.config_seed(2)
+    t_gen = time.time()
+    log(f"generating {n}x{fc}x{tc} input")
+    host = synth.make_input(seed, n, fc, tc)
+    t_gen = time.time() - t_gen
+    x = torch.from_numpy(host).to(dev)
+    torch.cuda.synchronize()
+
+    corr = corrx.Correlator(n, fc, tc, corrx.CORRX_LAYOUT_TFI, args.engine)
+    acc = corr.new_acc(dev)
+    order = corrx.CORRX_TRI_STATION_POL
+    dst = torch.empty(corrx.corr_dump_count(corr.h, order), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+
+    def step(k=None):
+        corr.zero(acc)
+        if k is not None:
+            ev[k][0].record(stream)
+        corr.xmac(x, acc)
+        if k is not None:
+            ev[k][1].record(stream)
+        corr.dump(acc, order, corrx.CORRX_F32, dst)
+
+    log(f"input ready ({time.time() - t_gen:.1f} s); warmup {args.warmup}, timed {args.steps}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / args.steps * 1e3
+    xmac_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    ops = model.alg_ops(n, fc, tc)
+    tops = ops / (ms_step * 1e-3) / 1e12
+    xmac_tops = ops / (xmac_ms * 1e-3) / 1e12
+
+    # correctness of the timed configuration on sampled channels
+    import oracle
+
+    check = []
+    rng = np.random.default_rng(0)
+    chans = sorted(set([0, fc - 1] + list(rng.integers(0, fc, size=max(0, args.check_channels - 2)))))
+    acc_h = acc.cpu().numpy()
+    for f in chans[: max(1, args.check_channels)]:
+        ch = np.ascontiguousarray(synth.channel_view(host, 0, n, fc, tc, f))
+        want = oracle.xmac(ch, n, 1, tc)[0]
+        check.append(bool(np.array_equal(acc_h[f].astype(np.int64), want)))
+
+    result = {
+        "metric": "X-engine TOPS + x real-time at 256 inputs (MFMA vs plain); p99 integration latency",
+        "value": round(tops, 2),
+        "unit": "TOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8" if args.engine in ("mfma_i8", "auto") else ("fp8" if args.engine == "mfma_f8" else "int32"),
+        "data": "synthetic",
+        "config": {"workload": f"full band: {n} inputs x {fc} channels x {tc} samples (1 s at 10 kHz), "
+                               "4+4-bit noise+tone, TFI layout; step = zero + xmac + dump(station-pol f32)",
+                   "engine": args.engine, "n_inputs": n, "n_chan": fc, "n_time": tc},
+        "xrt": round(model.realtime_factor(tc, ms_step * 1e-3), 1),
+        "xmac_ms": round(xmac_ms, 4),
+        "xmac_tops": round(xmac_tops, 2),
+        "xmac_xrt": round(model.realtime_factor(tc, xmac_ms * 1e-3), 1),
+        "parity_sampled_channels": {"channels": [int(c) for c in chans], "bit_exact": all(check)},
+        "input_gen_s": round(t_gen, 1),
+    }
+    peak = PEAK_FP8_TFLOPS if args.engine == "mfma_f8" else PEAK_INT8_TOPS
+    result["roofline"] = {
+        "bound": "mfma",
+        "achieved": round(xmac_tops, 2),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "op_kind": "algorithmic int8 ops (8 per complex MAC)" if args.engine != "mfma_f8" else
+                   "algorithmic fp8 ops (8 per complex MAC)",
+        "frac": round(xmac_tops / peak, 4),
+        "traffic": None,
+        "kernel": "xmac_diag_i8<256,64>" if args.engine in ("mfma_i8", "auto") else args.engine,
+    }
+
+    log(f"timed: {ms_step:.3f} ms/step, xmac {xmac_ms:.3f} ms; parity {check}")
+    if not args.no_extras:
+        result["extras"] = extras(corrx, model, synth, torch, dev, x, host, n, fc, tc)
+
+    del acc, dst
+    corr.close()
+
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a channel sample")
+        result["cpu_baseline"] = cpu_baseline(oracle, model, synth, host, n, fc, tc, args.cpu_channels)
+
+    print(json.dumps(result), flush=True)
+
+
+def time_xmac(corrx, torch, c, x, acc, reps):
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    c.zero(acc)
+    c.xmac(x, acc)
+    torch.cuda.synchronize()
+    for a, b in evs:
+        c.zero(acc)
+        a.record(s)
+        c.xmac(x, acc)
+        b.record(s)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
+    out = {}
+    # plain (vector ALU) engine on the same full-band input
+    c = corrx.Correlator(n, fc, tc, corrx.CORRX_LAYOUT_TFI, "plain")
+    acc = c.new_acc(dev)
+    ms = time_xmac(corrx, torch, c, x, acc, 3)
+    ops = model.alg_ops(n, fc, tc)
+    out["full_band_plain"] = {"xmac_ms": round(ms, 3), "tops": round(ops / ms / 1e9, 2),
+                              "xrt": round(model.realtime_factor(tc, ms * 1e-3), 1)}
+    c.close()
+    del acc
+    # one coarse channel: 256 inputs x 128 channels x 5000 samples, both engines
+    n2, f2, t2 = 256, 128, 5000
+    h2 = synth.make_input(synth.config_seed(1), n2, f2, t2)
+    x2 = torch.from_numpy(h2).to(dev)
+    for eng in ("mfma_i8", "plain"):
+        c = corrx.Correlator(n2, f2, t2, corrx.CORRX_LAYOUT_TFI, eng)
+        acc = c.new_acc(dev)
+        ms = time_xmac(corrx, torch, c, x2, acc, 20)
+        ops = model.alg_ops(n2, f2, t2)
+        out[f"coarse_channel_{eng}"] = {"xmac_ms": round(ms, 4), "tops": round(ops / ms / 1e9, 2),
+                                        "xrt": round(model.realtime_factor(t2, ms * 1e-3), 1)}
+        c.close()
+    return out
+
+
+def cpu_baseline(oracle, model, synth, host, n, fc, tc, n_ch):
+    threads = os.cpu_count() or 1
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    oracle.set_threads(threads)
+    used = oracle.get_threads()
+    n_ch = min(n_ch, fc)
+    sub = np.ascontiguousarray(host.reshape(tc, fc, n)[:, :n_ch, :]).reshape(-1)
+    t0 = time.perf_counter()
+    oracle.xmac(sub, n, n_ch, tc)
+    dt = time.perf_counter() - t0
+    ops = model.alg_ops(n, n_ch, tc)
+    return {"value": round(ops / dt / 1e12, 4), "unit": "TOPS", "cores": used, "kind": "oracle",
+            "sample": f"{n_ch} of {fc} channels x {tc} samples x {n} inputs (gcc -O2 -fopenmp int64 triple loop, "
+                      f"OpenMP over channels), {dt:.1f} s",
+            "xrt": round(model.realtime_factor(tc, dt * fc / n_ch), 4)}
+
+
+if __name__ == "__main__":
+    main()

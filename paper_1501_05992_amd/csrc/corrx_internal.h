@@ -14,6 +14,10 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
+// Word 3 of a raw buffer descriptor on gfx9-family parts (32-bit data format,
+// no swizzle): loads past num_records return 0.
+constexpr int kBufferRsrcWord3 = 0x00020000;
+
 // Largest time range one work unit integrates.  Bounds the biased int32 sums
 // of the MFMA engines (|G_b| <= 900 per sample) well inside int32.
 constexpr int kMaxUnitTime = 1 << 20;

@@ -77,35 +77,51 @@ __device__ inline int xcd_remap(int b, int n) {
   return (b % 8) * (n / 8) + b / 8;
 }
 
-// Load four consecutive input bytes of one time row (0 past the row end).
-__device__ inline uint32_t load4(const uint8_t* row, int i, int n_inputs, bool aligned) {
-  if (aligned && i + 3 < n_inputs)
-    return __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(row + i));
-  uint32_t v = 0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-    if (i + b < n_inputs) v |= uint32_t(row[i + b]) << (8 * b);
-  return v;
-}
-
 template <int NB, int TC>
 struct DiagUnit {
   using D = Diag<NB, TC>;
 
   // Load chunk c of the unit into registers.
-  __device__ static void load_chunk(const Problem& p, int f, int t0, int t1, int c, bool aligned,
+  //   ALIGNED (N % 4 == 0, 4-byte aligned buffer): raw buffer loads through a
+  //   descriptor that starts at the chunk's first row and ends at the end of
+  //   the channel's last valid row, so rows past the unit's time range read 0
+  //   in hardware; quads past N use an out-of-range offset.  No branch and no
+  //   select follows a load, so all 16 loads stay in flight.
+  //   Otherwise: byte loads (slow path).
+  template <bool ALIGNED>
+  __device__ static void load_chunk(const Problem& p, int f, int t0, int t1, int c, int64_t stride,
                                     uint32_t (&ld)[D::ITER][16]) {
+    const int tb = t0 + c * TC;
+    if constexpr (ALIGNED) {
+      const int rows = min(t1 - tb, TC);
+      const uint32_t nrec = (uint32_t)((rows - 1) * stride + p.n_inputs);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<uint8_t*>(p.in + row_offset(p, f, tb)), (short)0, (int)nrec, kBufferRsrcWord3);
 #pragma unroll
-    for (int k = 0; k < D::ITER; ++k) {
-      const int item = threadIdx.x + k * D::NT;
-      const int q = item % D::QUADS, s = item / D::QUADS;
-      const int tb = t0 + c * TC + 16 * s;
+      for (int k = 0; k < D::ITER; ++k) {
+        const int item = threadIdx.x + k * D::NT;
+        const int q = item % D::QUADS, s = item / D::QUADS;
+        const uint32_t off0 = 4 * q < p.n_inputs ? (uint32_t)(16 * s * stride + 4 * q) : 0x80000000u;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int t = tb + r;
-        ld[k][r] = (t < t1 && 4 * q < p.n_inputs)
-                       ? load4(p.in + row_offset(p, f, t), 4 * q, p.n_inputs, aligned)
-                       : 0u;
+        for (int r = 0; r < 16; ++r)
+          ld[k][r] = __builtin_amdgcn_raw_buffer_load_b32(rs, off0 + (uint32_t)(r * stride), 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < D::ITER; ++k) {
+        const int item = threadIdx.x + k * D::NT;
+        const int q = item % D::QUADS, s = item / D::QUADS;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int t = tb + 16 * s + r;
+          uint32_t v = 0;
+          if (t < t1) {
+            const uint8_t* row = p.in + row_offset(p, f, t);
+            for (int b = 0; b < 4; ++b)
+              if (4 * q + b < p.n_inputs) v |= uint32_t(row[4 * q + b]) << (8 * b);
+          }
+          ld[k][r] = v;
+        }
       }
     }
   }
@@ -190,47 +206,42 @@ struct DiagUnit {
           xa[(32 * x + acc_row(r, lane)) * D::XPITCH + 32 * y + (lane & 31)] = acc[x][y][r];
   }
 
-  // Combine this wave's block with its mirror (in xa) and add the lower
-  // triangle into the accumulator.
-  __device__ static void combine(const Problem& p, int f, const int* xa, const v16i (&acc)[D::TPW][D::TPW],
-                                 int lane, int ibase, int jbase, const uint32_t* s_sy, const uint32_t* s_sw,
-                                 uint32_t tproc, bool atomic) {
+  // All threads: combine the block of G_b at rows ib.., columns jb.. (in `own`)
+  // with its mirror block at rows jb.., columns ib.. (in `mir`; the same area
+  // for a diagonal block) and add the lower triangle into the accumulator.
+  __device__ static void combine(const Problem& p, int f, const int* own, const int* mir, int ib, int jb,
+                                 const uint32_t* s_sy, const uint32_t* s_sw, uint32_t tproc, bool atomic) {
     const int64_t nb = tri_index(p.n_inputs, 0);
     int* out = p.acc + (int64_t)f * nb * 2;
-#pragma unroll
-    for (int x = 0; x < D::TPW; ++x)
-#pragma unroll
-      for (int y = 0; y < D::TPW; ++y)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int il = 32 * x + acc_row(r, lane), jl = 32 * y + (lane & 31);
-          const int i = ibase + il, j = jbase + jl;
-          if (i < j || i >= p.n_inputs) continue;
-          const uint32_t gij = (uint32_t)acc[x][y][r];
-          const uint32_t gji = (uint32_t)xa[jl * D::XPITCH + il];
-          const uint32_t syi = s_sy[i], swi = s_sw[i], syj = s_sy[j], swj = s_sw[j];
-          const uint32_t ei = syi + 30u * swi, ej = syj + 30u * swj;
-          const uint32_t gi = syi - 2u * swi, gj = syj - 2u * swj;
-          const int re2 = (int)(gij + gji - ei - ej + 256u * tproc);
-          const int im2 = (int)(gji - gij + gi - gj);
-          int* o = out + 2 * tri_index(i, j);
-          if (atomic) {
-            atomicAdd(o, re2 >> 1);
-            atomicAdd(o + 1, im2 >> 1);
-          } else {
-            int2 v = *reinterpret_cast<int2*>(o);
-            v.x += re2 >> 1;
-            v.y += im2 >> 1;
-            *reinterpret_cast<int2*>(o) = v;
-          }
-        }
+    for (int idx = threadIdx.x; idx < D::WT * D::WT; idx += D::NT) {
+      const int il = idx / D::WT, jl = idx % D::WT;
+      const int i = ib + il, j = jb + jl;
+      if (i < j || i >= p.n_inputs) continue;
+      const uint32_t gij = (uint32_t)own[il * D::XPITCH + jl];
+      const uint32_t gji = (uint32_t)mir[jl * D::XPITCH + il];
+      const uint32_t syi = s_sy[i], swi = s_sw[i], syj = s_sy[j], swj = s_sw[j];
+      const uint32_t ei = syi + 30u * swi, ej = syj + 30u * swj;
+      const uint32_t gi = syi - 2u * swi, gj = syj - 2u * swj;
+      const int re2 = (int)(gij + gji - ei - ej + 256u * tproc);
+      const int im2 = (int)(gji - gij + gi - gj);
+      int* o = out + 2 * tri_index(i, j);
+      if (atomic) {
+        atomicAdd(o, re2 >> 1);
+        atomicAdd(o + 1, im2 >> 1);
+      } else {
+        int2 v = *reinterpret_cast<int2*>(o);
+        v.x += re2 >> 1;
+        v.y += im2 >> 1;
+        *reinterpret_cast<int2*>(o) = v;
+      }
+    }
   }
 };
 
 template <int NB>
 constexpr int diag_threads = NB >= 256 ? 256 : 64;
 
-template <int NB, int TC>
+template <int NB, int TC, bool ALIGNED>
 __global__ __launch_bounds__(diag_threads<NB>, 1) void xmac_diag_i8(Problem p, int nsplit, int tsplit) {
   using D = Diag<NB, TC>;
   using U = DiagUnit<NB, TC>;
@@ -243,8 +254,8 @@ __global__ __launch_bounds__(diag_threads<NB>, 1) void xmac_diag_i8(Problem p, i
   const int f = u / nsplit, sp = u % nsplit;
   const int t0 = sp * tsplit;
   const int t1 = min(p.n_time, t0 + tsplit);
-  const int nchunks = (t1 - t0 + TC - 1) / TC;
-  const bool aligned = (p.n_inputs % 4 == 0) && ((reinterpret_cast<uintptr_t>(p.in) & 3) == 0);
+  const int nchunks = t1 > t0 ? (t1 - t0 + TC - 1) / TC : 0;
+  const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
 
   for (int k = tid; k < NB; k += D::NT) {
     s_sy[k] = 0;
@@ -255,9 +266,7 @@ __global__ __launch_bounds__(diag_threads<NB>, 1) void xmac_diag_i8(Problem p, i
 #pragma unroll
   for (int x = 0; x < D::TPW; ++x)
 #pragma unroll
-    for (int y = 0; y < D::TPW; ++y)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[x][y][r] = 0;
+    for (int y = 0; y < D::TPW; ++y) acc[x][y] = v16i{0};
   uint32_t sy[D::ITER][4], sw[D::ITER][4];
 #pragma unroll
   for (int k = 0; k < D::ITER; ++k)
@@ -266,14 +275,14 @@ __global__ __launch_bounds__(diag_threads<NB>, 1) void xmac_diag_i8(Problem p, i
 
   uint32_t ld[D::ITER][16];
   if (nchunks > 0) {
-    U::load_chunk(p, f, t0, t1, 0, aligned, ld);
+    U::template load_chunk<ALIGNED>(p, f, t0, t1, 0, stride, ld);
     U::unpack_store(ld, lds, sy, sw);
   }
   __syncthreads();
 
   for (int c = 0; c < nchunks; ++c) {
     const bool more = c + 1 < nchunks;
-    if (more) U::load_chunk(p, f, t0, t1, c + 1, aligned, ld);
+    if (more) U::template load_chunk<ALIGNED>(p, f, t0, t1, c + 1, stride, ld);
     const uint8_t* st = lds + (c & 1) * D::STAGE;
 #pragma unroll
     for (int ks = 0; ks < D::KSTEPS; ++ks) {
@@ -314,22 +323,24 @@ __global__ __launch_bounds__(diag_threads<NB>, 1) void xmac_diag_i8(Problem p, i
   const uint32_t tproc = (uint32_t)(nchunks * TC);
   const bool atomic = nsplit > 1;
   int* xa = reinterpret_cast<int*>(lds);
+  int* xb = xa + (D::NXAREA - 1) * D::XAREA;
   if (D::WG == 1) {
     U::store_block(xa, acc, lane);
     __syncthreads();
-    U::combine(p, f, xa, acc, lane, 0, 0, s_sy, s_sw, tproc, atomic);
+    U::combine(p, f, xa, xa, 0, 0, s_sy, s_sw, tproc, atomic);
   } else {
-    // Round 1: block (0,1) and block (0,0) go to LDS; (1,0) and (0,0) combine.
+    // Off-diagonal quadrant (1,0) against its mirror (0,1).
     if (wave == 1) U::store_block(xa, acc, lane);
-    if (wave == 0) U::store_block(xa + D::XAREA, acc, lane);
+    if (wave == 2) U::store_block(xb, acc, lane);
     __syncthreads();
-    if (wave == 2) U::combine(p, f, xa, acc, lane, D::WT, 0, s_sy, s_sw, tproc, atomic);
-    if (wave == 0) U::combine(p, f, xa + D::XAREA, acc, lane, 0, 0, s_sy, s_sw, tproc, atomic);
+    U::combine(p, f, xb, xa, D::WT, 0, s_sy, s_sw, tproc, atomic);
     __syncthreads();
-    // Round 2: block (1,1) against itself.
-    if (wave == 3) U::store_block(xa, acc, lane);
+    // Diagonal quadrants (0,0) and (1,1), each against itself.
+    if (wave == 0) U::store_block(xa, acc, lane);
+    if (wave == 3) U::store_block(xb, acc, lane);
     __syncthreads();
-    if (wave == 3) U::combine(p, f, xa, acc, lane, D::WT, D::WT, s_sy, s_sw, tproc, atomic);
+    U::combine(p, f, xa, xa, 0, 0, s_sy, s_sw, tproc, atomic);
+    U::combine(p, f, xb, xb, D::WT, D::WT, s_sy, s_sw, tproc, atomic);
   }
 }
 
@@ -339,7 +350,13 @@ static int launch_diag(const Problem& p, int nsplit, hipStream_t s) {
   const int tsplit = (p.n_time + nsplit - 1) / nsplit;
   const int64_t grid = (int64_t)p.n_chan * nsplit;
   if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
-  hipLaunchKernelGGL((xmac_diag_i8<NB, TC>), dim3((unsigned)grid), dim3(D::NT), 0, s, p, nsplit, tsplit);
+  const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
+  const bool aligned = (p.n_inputs % 4 == 0) && ((reinterpret_cast<uintptr_t>(p.in) & 3) == 0) &&
+                       (int64_t)TC * stride + p.n_inputs < 0x7FFFFFFF;
+  if (aligned)
+    hipLaunchKernelGGL((xmac_diag_i8<NB, TC, true>), dim3((unsigned)grid), dim3(D::NT), 0, s, p, nsplit, tsplit);
+  else
+    hipLaunchKernelGGL((xmac_diag_i8<NB, TC, false>), dim3((unsigned)grid), dim3(D::NT), 0, s, p, nsplit, tsplit);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
