@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-engine and small-config lines")
     ap.add_argument("--cpu-channels", type=int, default=256, help="channels in the oracle's timed sample")
     ap.add_argument("--check-channels", type=int, default=2, help="channels checked against the oracle")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, run one 1 GiB device-to-device copy (calibrates traffic counters)")
     return ap.parse_args()
 
 
@@ -151,6 +153,12 @@ def main():
     }
 
     log(f"timed: {ms_step:.3f} ms/step, xmac {xmac_ms:.3f} ms; parity {check}")
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if not args.no_extras:
         result["extras"] = extras(corrx, model, synth, torch, dev, x, host, n, fc, tc)
 
