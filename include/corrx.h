@@ -127,7 +127,10 @@ int corr_zero(corrx_t h, void *acc, void *stream);
  *   acc: device, corr_acc_bytes(h) bytes, int32 [f][b][re, im], b = i(i+1)/2 + j.
  * The handle counts samples since the last corr_zero on the host; a call that
  * could overflow int32 (more than 21,913,098 samples, |Re|,|Im| <= 98 per
- * sample) returns CORRX_EOVERFLOW and enqueues nothing.
+ * sample) returns CORRX_EOVERFLOW and enqueues nothing.  The first corr_xmac
+ * after corr_zero on the same accumulator writes V instead of adding it (the
+ * accumulator is known to be zero), so the caller must not modify the
+ * accumulator between corr_zero and that call.
  */
 int corr_xmac(corrx_t h, const void *in, void *acc, void *stream);
 

@@ -15,6 +15,7 @@ struct corrx_ctx {
   int device;
   int n_cu;
   int64_t samples; // since the last corr_zero
+  void* zeroed;    // accumulator last set to zero by corr_zero (while samples == 0)
 };
 
 namespace {
@@ -82,6 +83,7 @@ int corr_create(int n_inputs, int n_chan, int n_time, int layout, corrx_t* out) 
   h->device = dev;
   h->n_cu = n_cu;
   h->samples = 0;
+  h->zeroed = nullptr;
   *out = h;
   return CORRX_OK;
 }
@@ -123,7 +125,10 @@ int64_t corr_samples(corrx_t h) { return h ? h->samples : CORRX_EINVAL; }
 int corr_zero(corrx_t h, void* acc, void* stream) {
   if (!h || !acc) return CORRX_EINVAL;
   const int rc = launch_zero(static_cast<int*>(acc), (int64_t)(corr_acc_bytes(h) / sizeof(int)), as_stream(stream));
-  if (rc == CORRX_OK) h->samples = 0;
+  if (rc == CORRX_OK) {
+    h->samples = 0;
+    h->zeroed = acc;
+  }
   return rc;
 }
 
@@ -138,12 +143,16 @@ int corr_xmac(corrx_t h, const void* in, void* acc, void* stream) {
   p.n_time = h->n_time;
   p.layout = h->layout;
   const int engine = resolve_engine(h->engine);
+  // A freshly zeroed accumulator (corr_zero on this handle and stream, no
+  // correlation since) is overwritten instead of read and added to.
+  const int mode = (h->samples == 0 && h->zeroed == acc) ? kWriteStore : kWriteAdd;
   int rc;
   if (engine == CORRX_ENGINE_PLAIN) {
     const int nbk = (h->n_inputs + 63) / 64;
-    rc = launch_plain(p, plan_splits(h->n_chan, nbk * (nbk + 1) / 2, h->n_time, h->n_cu), as_stream(stream));
+    rc = launch_plain(p, plan_splits(h->n_chan, nbk * (nbk + 1) / 2, h->n_time, h->n_cu), mode,
+                      as_stream(stream));
   } else {
-    rc = launch_mfma(p, engine, plan_splits(h->n_chan, 1, h->n_time, h->n_cu), CORRX_TILE_DEFAULT,
+    rc = launch_mfma(p, engine, plan_splits(h->n_chan, 1, h->n_time, h->n_cu), mode, CORRX_TILE_DEFAULT,
                      as_stream(stream));
   }
   if (rc == CORRX_OK) h->samples += h->n_time;

@@ -106,11 +106,18 @@ struct LaunchStatus {
   int status;
 };
 
+// How a kernel writes its results into the accumulator.
+enum WriteMode {
+  kWriteStore = 0,  // accumulator known to be zero and one writer per element: plain store
+  kWriteAdd = 1,    // one writer per element: read-modify-write
+  kWriteAtomic = 2  // several writers per element (time splits): atomic add
+};
+
 // int8 / fp8 MFMA engine over one problem.  nsplit: time splits per channel
 // (each at most kMaxUnitTime samples); atomic accumulation when nsplit > 1.
-int launch_mfma(const Problem& p, int engine, int nsplit, int tile_cfg, hipStream_t s);
+int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, hipStream_t s);
 // vector-ALU engine.
-int launch_plain(const Problem& p, int nsplit, hipStream_t s);
+int launch_plain(const Problem& p, int nsplit, int mode, hipStream_t s);
 // accumulator fill, dump and incoherent beam.
 int launch_zero(int* acc, int64_t n_words, hipStream_t s);
 int launch_dump(const int* acc, int n_inputs, int n_chan, int order, int dtype, void* dst, hipStream_t s);

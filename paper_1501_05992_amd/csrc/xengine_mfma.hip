@@ -299,32 +299,50 @@ struct DiagUnit {
 
   // All threads: combine the quadrant of G_b at rows ib.., columns jb.. (in
   // `own`) with its mirror quadrant at rows jb.., columns ib.. (in `mir`; the
-  // same area for a diagonal quadrant) and add the lower triangle into the
-  // accumulator.
+  // same area for a diagonal quadrant) and write the lower triangle into the
+  // accumulator.  s_e / s_g: per-input correction terms.  Eight elements per
+  // thread are in flight at a time, so read-modify-write latencies overlap.
   __device__ static void combine(const Problem& p, int f, const int* own, const int* mir, int ib, int jb,
-                                 const uint32_t* s_sy, const uint32_t* s_sw, uint32_t tproc, bool atomic) {
+                                 const int* s_e, const int* s_g, uint32_t tproc, int mode) {
+    constexpr int UN = 8;
     const int64_t nb = tri_index(p.n_inputs, 0);
-    int* out = p.acc + (int64_t)f * nb * 2;
-    for (int idx = threadIdx.x; idx < D::H * D::H; idx += D::NT) {
-      const int il = idx / D::H, jl = idx % D::H;
-      const int i = ib + il, j = jb + jl;
-      if (i < j || i >= p.n_inputs) continue;
-      const uint32_t gij = (uint32_t)own[il * D::XPITCH + jl];
-      const uint32_t gji = (uint32_t)mir[jl * D::XPITCH + il];
-      const uint32_t syi = s_sy[i], swi = s_sw[i], syj = s_sy[j], swj = s_sw[j];
-      const uint32_t ei = syi + 30u * swi, ej = syj + 30u * swj;
-      const uint32_t gi = syi - 2u * swi, gj = syj - 2u * swj;
-      const int re2 = (int)(gij + gji - ei - ej + 256u * tproc);
-      const int im2 = (int)(gji - gij + gi - gj);
-      int* o = out + 2 * tri_index(i, j);
-      if (atomic) {
-        atomicAdd(o, re2 >> 1);
-        atomicAdd(o + 1, im2 >> 1);
+    int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
+    for (int base = threadIdx.x; base < D::H * D::H; base += D::NT * UN) {
+      int2 val[UN];
+      int64_t pos[UN];
+      bool ok[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int idx = base + u * D::NT;
+        const int il = (idx / D::H) % D::H, jl = idx % D::H;
+        const int i = ib + il, j = jb + jl;
+        ok[u] = idx < D::H * D::H && i >= j && i < p.n_inputs;
+        const uint32_t gij = (uint32_t)own[il * D::XPITCH + jl];
+        const uint32_t gji = (uint32_t)mir[jl * D::XPITCH + il];
+        const int ii = min(i, NB - 1), jj = min(j, NB - 1);
+        const int re2 = (int)(gij + gji - (uint32_t)s_e[ii] - (uint32_t)s_e[jj] + 256u * tproc);
+        const int im2 = (int)(gji - gij + (uint32_t)s_g[ii] - (uint32_t)s_g[jj]);
+        val[u] = make_int2(re2 >> 1, im2 >> 1);
+        pos[u] = ok[u] ? tri_index(i, j) : 0;
+      }
+      if (mode == kWriteStore) {
+#pragma unroll
+        for (int u = 0; u < UN; ++u)
+          if (ok[u]) out[pos[u]] = val[u];
+      } else if (mode == kWriteAdd) {
+        int2 old[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) old[u] = out[pos[u]];
+#pragma unroll
+        for (int u = 0; u < UN; ++u)
+          if (ok[u]) out[pos[u]] = make_int2(old[u].x + val[u].x, old[u].y + val[u].y);
       } else {
-        int2 v = *reinterpret_cast<int2*>(o);
-        v.x += re2 >> 1;
-        v.y += im2 >> 1;
-        *reinterpret_cast<int2*>(o) = v;
+#pragma unroll
+        for (int u = 0; u < UN; ++u)
+          if (ok[u]) {
+            __hip_atomic_fetch_add(&out[pos[u]].x, val[u].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&out[pos[u]].y, val[u].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
       }
     }
   }
@@ -335,7 +353,7 @@ constexpr int diag_min_blocks = NT >= 512 ? 1 : 2;
 
 template <int NB, int TC, int WC, bool ALIGNED>
 __global__ __launch_bounds__(128 * WC, diag_min_blocks<128 * WC>) void xmac_diag_i8(Problem p, int nsplit,
-                                                                                  int tsplit) {
+                                                                                  int tsplit, int mode) {
   using D = Diag<NB, TC, WC>;
   using U = DiagUnit<NB, TC, WC>;
   static_assert(D::NT == 128 * WC, "thread count must match the launch bounds");
@@ -395,7 +413,8 @@ __global__ __launch_bounds__(128 * WC, diag_min_blocks<128 * WC>) void xmac_diag
     U::template chunk_step<ALIGNED, false, false>(p, f, t0, t1, c, stride, lds, rrow, crow, ld, acc, sy, sw, s_bad,
                                                   s_sy, s_sw);
 
-  // Per-input sums of this unit.
+  // Per-input sums of this unit, then the correction terms
+  // e_k = Sy_k + 30 Sw_k and g_k = Sy_k - 2 Sw_k (in place).
 #pragma unroll
   for (int k = 0; k < D::ITER; ++k) {
     if (!U::has_item(k)) continue;
@@ -407,9 +426,17 @@ __global__ __launch_bounds__(128 * WC, diag_min_blocks<128 * WC>) void xmac_diag
     }
   }
   __syncthreads();
+  for (int k = tid; k < NB; k += D::NT) {
+    const uint32_t y = s_sy[k], w = s_sw[k];
+    s_sy[k] = y + 30u * w;
+    s_sw[k] = y - 2u * w;
+  }
+  __syncthreads();
+  const int* s_e = reinterpret_cast<const int*>(s_sy);
+  const int* s_g = reinterpret_cast<const int*>(s_sw);
 
   const uint32_t tproc = (uint32_t)(nchunks * TC);
-  const bool atomic = nsplit > 1;
+  const int wmode = nsplit > 1 ? kWriteAtomic : mode;
   int* xa = reinterpret_cast<int*>(lds);
   int* xb = xa + D::XAREA;
   constexpr int HW = WC / 2;  // wave columns per quadrant
@@ -417,18 +444,18 @@ __global__ __launch_bounds__(128 * WC, diag_min_blocks<128 * WC>) void xmac_diag
   if (wr == 0 && wc >= HW) U::store_tile(xa, (wc - HW) * D::TN, acc, lane);
   if (wr == 1 && wc < HW) U::store_tile(xb, wc * D::TN, acc, lane);
   __syncthreads();
-  U::combine(p, f, xb, xa, D::H, 0, s_sy, s_sw, tproc, atomic);
+  U::combine(p, f, xb, xa, D::H, 0, s_e, s_g, tproc, wmode);
   __syncthreads();
   // Round 2: the diagonal quadrants (0,0) and (1,1), each against itself.
   if (wr == 0 && wc < HW) U::store_tile(xa, wc * D::TN, acc, lane);
   if (wr == 1 && wc >= HW) U::store_tile(xb, (wc - HW) * D::TN, acc, lane);
   __syncthreads();
-  U::combine(p, f, xa, xa, 0, 0, s_sy, s_sw, tproc, atomic);
-  U::combine(p, f, xb, xb, D::H, D::H, s_sy, s_sw, tproc, atomic);
+  U::combine(p, f, xa, xa, 0, 0, s_e, s_g, tproc, wmode);
+  U::combine(p, f, xb, xb, D::H, D::H, s_e, s_g, tproc, wmode);
 }
 
 template <int NB, int TC, int WC>
-static int launch_diag(const Problem& p, int nsplit, hipStream_t s) {
+static int launch_diag(const Problem& p, int nsplit, int mode, hipStream_t s) {
   using D = Diag<NB, TC, WC>;
   const int tsplit = (p.n_time + nsplit - 1) / nsplit;
   const int64_t grid = (int64_t)p.n_chan * nsplit;
@@ -438,19 +465,19 @@ static int launch_diag(const Problem& p, int nsplit, hipStream_t s) {
                        (int64_t)TC * stride + p.n_inputs < 0x7FFFFFFF;
   if (aligned)
     hipLaunchKernelGGL((xmac_diag_i8<NB, TC, WC, true>), dim3((unsigned)grid), dim3(D::NT), 0, s, p, nsplit,
-                       tsplit);
+                       tsplit, mode);
   else
     hipLaunchKernelGGL((xmac_diag_i8<NB, TC, WC, false>), dim3((unsigned)grid), dim3(D::NT), 0, s, p, nsplit,
-                       tsplit);
+                       tsplit, mode);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
-int launch_mfma(const Problem& p, int engine, int nsplit, int tile_cfg, hipStream_t s) {
+int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, hipStream_t s) {
   if (engine != CORRX_ENGINE_MFMA_I8) return CORRX_EUNSUPPORTED;
   (void)tile_cfg;
-  if (p.n_inputs <= 64) return launch_diag<64, 64, 2>(p, nsplit, s);
-  if (p.n_inputs <= 128) return launch_diag<128, 64, 2>(p, nsplit, s);
-  if (p.n_inputs <= 256) return launch_diag<256, 64, 4>(p, nsplit, s);
+  if (p.n_inputs <= 64) return launch_diag<64, 64, 2>(p, nsplit, mode, s);
+  if (p.n_inputs <= 128) return launch_diag<128, 64, 2>(p, nsplit, mode, s);
+  if (p.n_inputs <= 256) return launch_diag<256, 64, 4>(p, nsplit, mode, s);
   return CORRX_EUNSUPPORTED;
 }
 

@@ -41,7 +41,7 @@ __device__ inline uint8_t load1(const Problem& p, int f, int t, int i, int t1) {
 
 }  // namespace
 
-__global__ __launch_bounds__(kThreads) void xmac_plain(Problem p, int ntiles, int nsplit, int tsplit) {
+__global__ __launch_bounds__(kThreads) void xmac_plain(Problem p, int ntiles, int nsplit, int tsplit, int mode) {
   __shared__ uint32_t sP[kPairs][kTile];   // row block, P
   __shared__ uint32_t sQ[kPairs][kTile];   // row block, Q
   __shared__ uint32_t sC[kPairs][kTile];   // column block, P
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void xmac_plain(Problem p, int ntiles, in
 
   const int64_t nb = tri_index(p.n_inputs, 0);
   int* out = p.acc + (int64_t)f * nb * 2;
-  const bool atomic = nsplit > 1;
+  const int wmode = nsplit > 1 ? kWriteAtomic : mode;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -120,23 +120,26 @@ __global__ __launch_bounds__(kThreads) void xmac_plain(Problem p, int ntiles, in
       const int i = i0 + 4 * tr + a, j = j0 + 4 * tc + b;
       if (i >= p.n_inputs || j > i) continue;
       int* o = out + 2 * tri_index(i, j);
-      if (atomic) {
+      if (wmode == kWriteAtomic) {
         atomicAdd(o, re_acc[a][b]);
         atomicAdd(o + 1, im_acc[a][b]);
-      } else {
+      } else if (wmode == kWriteAdd) {
         o[0] += re_acc[a][b];
         o[1] += im_acc[a][b];
+      } else {
+        o[0] = re_acc[a][b];
+        o[1] = im_acc[a][b];
       }
     }
 }
 
-int launch_plain(const Problem& p, int nsplit, hipStream_t s) {
+int launch_plain(const Problem& p, int nsplit, int mode, hipStream_t s) {
   const int nbk = (p.n_inputs + kTile - 1) / kTile;
   const int ntiles = nbk * (nbk + 1) / 2;
   const int tsplit = (p.n_time + nsplit - 1) / nsplit;
   const int64_t grid = (int64_t)p.n_chan * ntiles * nsplit;
   if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
-  hipLaunchKernelGGL(xmac_plain, dim3((unsigned)grid), dim3(kThreads), 0, s, p, ntiles, nsplit, tsplit);
+  hipLaunchKernelGGL(xmac_plain, dim3((unsigned)grid), dim3(kThreads), 0, s, p, ntiles, nsplit, tsplit, mode);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
