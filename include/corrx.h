@@ -165,13 +165,22 @@ typedef struct {
 
 /*
  * Plan a batch of n arrays (1 <= n <= 64) of uneven shapes, run by one
- * persistent launch that pulls work items (array, channel, tile, time range)
- * from a device queue.  engine: CORRX_ENGINE_MFMA_I8 or AUTO.  Allocates the
- * device work list and queue counter (freed by corr_batch_destroy).
- * tile_cfg: per-array tile-shape code from the autotuner (NULL = built-in
- * choice); each code is a CORRX_TILE_* value.
+ * persistent launch: one workgroup per compute unit pulls work items (array,
+ * channel, tile, time range) from a device queue, longest first.  Each array
+ * needs n_inputs % 4 == 0 and 4-byte aligned input (else CORRX_EUNSUPPORTED).
+ * engine: CORRX_ENGINE_MFMA_I8 or AUTO.  Allocates the device work list and
+ * the queue counter (freed by corr_batch_destroy).
+ * tile_cfg: NULL (built-in choice) or one code per array, chosen by the
+ * autotuner: (unit) | (time_splits << 8), with unit a CORRX_TILE_* value
+ * (the input block a work item stages) and time_splits 0 for automatic or the
+ * number of time ranges per channel.
  */
-enum { CORRX_TILE_DEFAULT = 0, CORRX_TILE_T64 = 1, CORRX_TILE_T32 = 2 };
+enum {
+    CORRX_TILE_DEFAULT = 0, /* smallest unit that holds the array's inputs */
+    CORRX_TILE_UNIT64 = 1,  /* 64-input units, two channels per work item (N <= 64) */
+    CORRX_TILE_UNIT128 = 2, /* 128-input units, two channels per work item (N <= 128) */
+    CORRX_TILE_UNIT256 = 3  /* 256-input diagonal blocks plus pair units (any N) */
+};
 int corr_batch_create(const corrx_desc *descs, int n, int engine, const int *tile_cfg,
                       corrx_batch_t *out);
 int corr_batch_destroy(corrx_batch_t b);
@@ -179,9 +188,14 @@ int corr_batch_destroy(corrx_batch_t b);
 /* Work items in the plan (for reporting). */
 int64_t corr_batch_items(corrx_batch_t b);
 
+/* The plan of one array: internal unit kind (0: 256-input blocks, 2: 128-input
+ * pairs of channels, 3: 64-input pairs of channels) and time splits. */
+int corr_batch_plan(corrx_batch_t b, int array, int *kind, int *splits);
+
 /*
  * For every array a: accs[a] += V(ins[a]).  ins and accs are HOST arrays of n
- * DEVICE pointers (same meaning as for corr_xmac, one per array).  One launch.
+ * DEVICE pointers (same meaning as for corr_xmac, one per array; accs 8-byte
+ * aligned).  One persistent launch (plus a one-thread queue reset) on `stream`.
  */
 int corr_batch_xmac(corrx_batch_t b, const void *const *ins, void *const *accs, void *stream);
 

@@ -35,8 +35,9 @@ CORRX_ENGINE_PLAIN = 1
 CORRX_ENGINE_MFMA_I8 = 2
 CORRX_ENGINE_MFMA_F8 = 3
 CORRX_TILE_DEFAULT = 0
-CORRX_TILE_T64 = 1
-CORRX_TILE_T32 = 2
+CORRX_TILE_UNIT64 = 1
+CORRX_TILE_UNIT128 = 2
+CORRX_TILE_UNIT256 = 3
 
 ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
            "mfma_i8": CORRX_ENGINE_MFMA_I8, "mfma_f8": CORRX_ENGINE_MFMA_F8}
@@ -45,7 +46,7 @@ ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
 SYMBOLS = ("corr_abi_version", "corr_strerror", "corr_create", "corr_destroy", "corr_set_engine",
            "corr_get_engine", "corr_acc_bytes", "corr_dump_count", "corr_zero", "corr_xmac",
            "corr_dump", "corr_samples", "corr_beam", "corr_batch_create", "corr_batch_destroy",
-           "corr_batch_items", "corr_batch_xmac")
+           "corr_batch_items", "corr_batch_plan", "corr_batch_xmac")
 
 
 class CorrxError(RuntimeError):
@@ -89,6 +90,7 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(vp)], i),
             "corr_batch_destroy": ([vp], i),
             "corr_batch_items": ([vp], i64),
+            "corr_batch_plan": ([vp, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
             "corr_batch_xmac": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp], i),
         }
         for name, (args, res) in sig.items():
@@ -194,6 +196,12 @@ def corr_batch_items(b: int) -> int:
     return int(_check(lib().corr_batch_items(b), "corr_batch_items"))
 
 
+def corr_batch_plan(b: int, array: int) -> tuple[int, int]:
+    kind, splits = ctypes.c_int(), ctypes.c_int()
+    _check(lib().corr_batch_plan(b, array, ctypes.byref(kind), ctypes.byref(splits)), "corr_batch_plan")
+    return kind.value, splits.value
+
+
 def corr_batch_xmac(b: int, ins, accs, stream=None) -> None:
     n = len(ins)
     pin = (ctypes.c_void_p * n)(*[_ptr(x) for x in ins])
@@ -259,3 +267,36 @@ class Correlator:
     @property
     def samples(self) -> int:
         return corr_samples(self.h)
+
+
+class Batch:
+    """Arrays of uneven shapes correlated by one persistent launch."""
+
+    def __init__(self, descs, engine: int = CORRX_ENGINE_AUTO, tile_cfg=None):
+        self.descs = [tuple(d) for d in descs]
+        self.h = corr_batch_create(self.descs, engine, tile_cfg)
+
+    def close(self) -> None:
+        if self.h:
+            corr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def items(self) -> int:
+        return corr_batch_items(self.h)
+
+    def plan(self, array: int) -> tuple[int, int]:
+        return corr_batch_plan(self.h, array)
+
+    def new_accs(self, device="cuda"):
+        return [torch.zeros((f, n * (n + 1) // 2, 2), dtype=torch.int32, device=device)
+                for (n, f, t, lay) in self.descs]
+
+    def xmac(self, ins, accs, stream=None) -> None:
+        corr_batch_xmac(self.h, ins, accs, stream)

@@ -152,8 +152,8 @@ int corr_xmac(corrx_t h, const void* in, void* acc, void* stream) {
     rc = launch_plain(p, plan_splits(h->n_chan, nbk * (nbk + 1) / 2, h->n_time, h->n_cu), mode,
                       as_stream(stream));
   } else {
-    rc = launch_mfma(p, engine, plan_splits(h->n_chan, 1, h->n_time, h->n_cu), mode, CORRX_TILE_DEFAULT,
-                     as_stream(stream));
+    rc = launch_mfma(p, engine, plan_splits(h->n_chan, mfma_units_per_channel(h->n_inputs), h->n_time, h->n_cu),
+                     mode, CORRX_TILE_DEFAULT, as_stream(stream));
   }
   if (rc == CORRX_OK) h->samples += h->n_time;
   return rc;

@@ -108,14 +108,17 @@ struct LaunchStatus {
 
 // How a kernel writes its results into the accumulator.
 enum WriteMode {
-  kWriteStore = 0,  // accumulator known to be zero and one writer per element: plain store
-  kWriteAdd = 1,    // one writer per element: read-modify-write
-  kWriteAtomic = 2  // several writers per element (time splits): atomic add
+  kWriteStore = 0,   // accumulator known to be zero and one writer per element: plain store
+  kWriteAdd = 1,     // one writer per element: read-modify-write
+  kWriteAtomic = 2,  // several writers per element (time splits): atomic add
+  kWriteNone = 3     // padding unit: compute, write nothing
 };
 
 // int8 / fp8 MFMA engine over one problem.  nsplit: time splits per channel
 // (each at most kMaxUnitTime samples); atomic accumulation when nsplit > 1.
 int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, hipStream_t s);
+// Work units per channel of the MFMA engine (diagonal blocks + pair units).
+int mfma_units_per_channel(int n_inputs);
 // vector-ALU engine.
 int launch_plain(const Problem& p, int nsplit, int mode, hipStream_t s);
 // accumulator fill, dump and incoherent beam.
@@ -125,25 +128,31 @@ int launch_beam(const Problem& p, int* out, hipStream_t s);
 
 // ---- persistent batched engine ---------------------------------------------
 
+// Unit kinds of the batch kernel.
+enum UnitKind {
+  kUnitDiag256 = 0,   // one 256-input diagonal block (tile = block index)
+  kUnitPair = 1,      // one pair unit (tile = pair index: block pair * 2 + half)
+  kUnitDiag128x2 = 2, // two 128-input channels (f, f+1) side by side
+  kUnitDiag64x2 = 3   // two 64-input channels side by side
+};
+
+constexpr int kMaxBatch = 64;
+
 // One work item of the persistent kernel.
 struct WorkItem {
-  int array;     // index into the batch's problem table
-  int channel;
-  int tile;      // unit index within the channel (see unit decoding in the kernel)
-  int t0;        // first sample
-  int t1;        // one past the last sample
-  int kind;      // unit kind and shape code
+  int array;    // index into BatchArgs::arrays
+  int channel;  // channel (first of two for the x2 kinds)
+  int tile;     // block / pair index within the channel
+  int t0, t1;   // sample range
+  int kind;     // UnitKind
+  int atomic;   // several items write the same elements (time splits)
 };
 
-struct BatchArray {
-  Problem p;
-  int nsplit;     // time splits per (channel, tile)
-  int units;      // units per channel
-  int unit_kind;  // shape code of this array's units
+struct BatchArgs {
+  Problem arrays[kMaxBatch];
 };
 
-int launch_batch(const BatchArray* d_arrays, const WorkItem* d_items, int64_t n_items, int* d_counter,
-                 int grid, hipStream_t s);
-int batch_max_grid();
+int launch_batch(const BatchArgs& args, const WorkItem* d_items, int n_items, int* d_counter, int grid,
+                 hipStream_t s);
 
 }  // namespace corrx

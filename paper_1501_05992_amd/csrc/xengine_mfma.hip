@@ -17,9 +17,17 @@
 // identities are exact integer algebra; every sum stays inside int32 for
 // T <= 2^20 samples per work unit.
 //
-// Kernel structure (one workgroup = one channel x one time range, the
-// "diagonal unit" of NB inputs, 2 x WC waves, two waves per SIMD so that one
-// wave's vector-ALU and LDS work overlaps the other's MFMAs):
+// Work units.  A channel's N x N square of G_b is tiled by blocks of 256
+// inputs.  A diagonal unit computes one diagonal block (NB = 64, 128 or 256
+// inputs) in full and pairs each element with its transpose through LDS.  A
+// pair unit takes 128 rows I of an off-diagonal block and the 256 columns J
+// and computes both G_b[I][J] = A_I B_J^T and G_b[J][I]^T = B_I A_J^T, so the
+// two halves of every baseline meet in registers.  Units run as standalone
+// grids (one launch per unit kind) or inside the persistent batch kernel.
+//
+// Unit structure (one workgroup = one unit x one time range, 8 waves for the
+// 256-input units, two waves per SIMD so that one wave's vector-ALU and LDS
+// work overlaps the other's MFMAs):
 //   - global -> registers: raw buffer loads of 8 time rows x 4 inputs per
 //     thread (lanes cover consecutive inputs of one row: coalesced), one chunk
 //     of TC samples ahead of the chunk being multiplied; rows past the time
@@ -42,54 +50,34 @@
 
 namespace corrx {
 
-template <int NB, int TC, int WC>
-struct Diag {
-  static constexpr int WR = 2;                       // wave rows
-  static constexpr int NW = WR * WC;                 // waves per workgroup
-  static constexpr int NT = 64 * NW;                 // threads per workgroup
-  static constexpr int TM = NB / WR;                 // wave tile rows
-  static constexpr int TN = NB / WC;                 // wave tile columns
-  static constexpr int FM = TM / 32;                 // 32x32 MFMA tiles along rows
-  static constexpr int FN = TN / 32;                 // ... along columns
-  static constexpr int ROWB = 2 * TC;                // staged bytes per input and chunk
-  static constexpr int CHUNKS = ROWB / 16;           // 16-byte chunks per row (8 samples each)
-  static constexpr int KSTEPS = TC / 16;             // K=32 (16-sample) MFMA steps per chunk
-  static constexpr int QUADS = NB / 4;
+// ---- staging of packed samples into LDS ---------------------------------------
+
+// ROWS inputs staged per chunk of TC samples by NT threads.  Stage row r holds
+// the A-operand bytes of one input: 16-byte chunk k = samples 8k..8k+7 as
+// [u(4), w(4), u(4), w(4)], chunks XOR-swizzled per row.
+template <int ROWS, int TC, int NT>
+struct Stage {
+  static constexpr int QUADS = ROWS / 4;
   static constexpr int GROUPS = TC / 8;              // 8-row groups per chunk
   static constexpr int ITEMS = QUADS * GROUPS;       // unpack items (8 rows x 4 inputs)
-  static constexpr int ITER = ITEMS >= NT ? ITEMS / NT : 1;
-  static constexpr bool PARTIAL = ITEMS < NT;        // some threads idle in the unpack
-  static constexpr int STAGE = NB * ROWB;            // bytes of one stage buffer
-  static constexpr int H = NB / 2;                   // quadrant side
-  static constexpr int XPITCH = H + 1;
-  static constexpr int XAREA = H * XPITCH;           // int32 words of one exchange area
-  static constexpr int LDS = (2 * STAGE > 2 * XAREA * 4) ? 2 * STAGE : 2 * XAREA * 4;
-  static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tiles are made of 32x32 MFMA tiles");
-  static_assert(PARTIAL || ITEMS % NT == 0, "unpack work must divide evenly");
-  static_assert(KSTEPS == 4, "the unpack is split into four phases, one per K-step");
-  static_assert(CHUNKS == 8, "swizzle assumes 8 chunks per row");
-  static_assert(WC % 2 == 0, "quadrants are made of whole wave tiles");
-};
+  static constexpr int ITER = (ITEMS + NT - 1) / NT;
+  static constexpr bool EXACT = ITEMS % NT == 0;
+  static constexpr int ROWB = 2 * TC;                // bytes per row and chunk
+  static constexpr int BYTES = ROWS * ROWB;          // one stage buffer
+  static constexpr int KSTEPS = TC / 16;             // K=32 (16-sample) MFMA steps per chunk
+  static_assert(KSTEPS == 4 && ROWB == 128, "the unpack is split into four phases over 8 chunks per row");
 
-// Row-dependent XOR swizzle of 16-byte chunks: conflict-free for the unpack
-// writes (rows 4l + c across lanes) and the fragment reads (rows r0 + m).
-__device__ inline int swz(int row) { return (row ^ (row >> 2)) & 7; }
+  // Stage quad q -> first input: the first `split` quads start at base0, the
+  // rest at base1.
+  struct Map {
+    int base0, split, base1;
+    __device__ int input(int q) const { return q < split ? base0 + 4 * q : base1 + 4 * (q - split); }
+  };
 
-// Map the hardware workgroup id so that consecutive logical units land on the
-// same XCD (ids are dealt round-robin over 8 XCDs): neighbouring channels then
-// share an L2.
-__device__ inline int xcd_remap(int b, int n) {
-  if (n % 8) return b;
-  return (b % 8) * (n / 8) + b / 8;
-}
+  __device__ static int swz(int row) { return (row ^ (row >> 2)) & 7; }
+  __device__ static bool has_item(int tid, int k) { return EXACT || tid + k * NT < ITEMS; }
 
-template <int NB, int TC, int WC>
-struct DiagUnit {
-  using D = Diag<NB, TC, WC>;
-
-  __device__ static bool has_item(int k) { return !D::PARTIAL || (int)threadIdx.x + k * D::NT < D::ITEMS; }
-
-  // Load the 8 rows x 4 inputs of this thread's unpack items of chunk c.
+  // Load the 8 rows x 4 inputs of this thread's items of chunk c.
   //   ALIGNED (N % 4 == 0, 4-byte aligned buffer): raw buffer loads through a
   //   descriptor that starts at the chunk's first row and ends at the end of
   //   the channel's last valid row, so rows past the unit's time range read 0
@@ -97,37 +85,46 @@ struct DiagUnit {
   //   select follows a load, so all loads stay in flight.
   //   Otherwise: byte loads (slow path).
   template <bool ALIGNED>
-  __device__ static void load_chunk(const Problem& p, int f, int t0, int t1, int c, int64_t stride,
-                                    uint32_t (&ld)[D::ITER][8]) {
+  __device__ static void load(const Problem& p, const Map& m, int f, int t0, int t1, int c, int64_t stride, int tid,
+                              uint32_t (&ld)[ITER][8]) {
     const int tb = t0 + c * TC;
     if constexpr (ALIGNED) {
+      // Row r of an item uses a descriptor whose base is advanced by r rows
+      // (scalar arithmetic) and whose range ends at the channel's last valid
+      // row, so the per-lane offset is the same for all 8 rows of the item.
       const int rows = min(t1 - tb, TC);
-      const uint32_t nrec = (uint32_t)((rows - 1) * stride + p.n_inputs);
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<uint8_t*>(p.in + row_offset(p, f, tb)), (short)0, (int)nrec, kBufferRsrcWord3);
+      const int64_t nrec0 = (int64_t)(rows - 1) * stride + p.n_inputs;
+      const uint8_t* base = p.in + row_offset(p, f, tb);
+      uint32_t off[ITER];
 #pragma unroll
-      for (int k = 0; k < D::ITER; ++k) {
-        const int item = threadIdx.x + k * D::NT;
-        const int q = item % D::QUADS, g = item / D::QUADS;
-        const uint32_t off0 =
-            (4 * q < p.n_inputs && has_item(k)) ? (uint32_t)(8 * g * stride + 4 * q) : 0x80000000u;
+      for (int k = 0; k < ITER; ++k) {
+        const int item = tid + k * NT;
+        const int q = item % QUADS, g = item / QUADS;
+        const int i = m.input(q);
+        off[k] = (i < p.n_inputs && has_item(tid, k)) ? (uint32_t)(8 * g * stride + i) : 0x80000000u;
+      }
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
-          ld[k][r] = __builtin_amdgcn_raw_buffer_load_b32(rs, off0 + (uint32_t)(r * stride), 0, 0);
+      for (int r = 0; r < 8; ++r) {
+        const int64_t nr = nrec0 - (int64_t)r * stride;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t*>(base + (int64_t)r * stride), (short)0, (int)(nr > 0 ? nr : 0), kBufferRsrcWord3);
+#pragma unroll
+        for (int k = 0; k < ITER; ++k) ld[k][r] = __builtin_amdgcn_raw_buffer_load_b32(rs, off[k], 0, 0);
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < D::ITER; ++k) {
-        const int item = threadIdx.x + k * D::NT;
-        const int q = item % D::QUADS, g = item / D::QUADS;
+      for (int k = 0; k < ITER; ++k) {
+        const int item = tid + k * NT;
+        const int q = item % QUADS, g = item / QUADS;
+        const int i = m.input(q);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           const int t = tb + 8 * g + r;
           uint32_t v = 0;
-          if (t < t1 && has_item(k)) {
+          if (t < t1 && has_item(tid, k)) {
             const uint8_t* row = p.in + row_offset(p, f, t);
             for (int b = 0; b < 4; ++b)
-              if (4 * q + b < p.n_inputs) v |= uint32_t(row[4 * q + b]) << (8 * b);
+              if (i + b < p.n_inputs) v |= uint32_t(row[i + b]) << (8 * b);
           }
           ld[k][r] = v;
         }
@@ -136,67 +133,86 @@ struct DiagUnit {
   }
 
   // Unpack of one chunk, in four phases (one per K-step of the previous
-  // chunk).  Phases 0/1: transpose rows 0-3 / 4-7 (time-major -> input-major)
-  // and bias; phases 2/3: inputs 0-1 / 2-3 of each quad -- byte sums and one
-  // 16-byte store per input [u(4), w(4), u(4), w(4)].  Invalid codes only set
-  // `bad`; a later fix-up pass zeroes those samples.
+  // chunk).  One item per thread: phases 0/1 transpose rows 0-3 / 4-7
+  // (time-major -> input-major) and bias; phases 2/3 handle inputs 0-1 / 2-3
+  // of the quad -- byte sums and one 16-byte store per input.  Two items per
+  // thread: phases 0/1 transpose / store item 0, phases 2/3 item 1, so only
+  // one item's transposed words are live at a time.  Invalid codes only set
+  // `bad`; the fix-up pass zeroes those samples.
+  static_assert(ITER <= 2, "at most two unpack items per thread");
+  static constexpr int LOAD_PHASE = ITER == 1 ? 1 : 2;  // last phase that reads the loaded words
+
+  __device__ static void transpose_tq(const uint32_t (&ld)[ITER][8], uint32_t (&y)[8], int k, int tq, uint32_t& bad) {
+    uint32_t e0, e1, e2, e3;
+    transpose4x4(ld[k][4 * tq], ld[k][4 * tq + 1], ld[k][4 * tq + 2], ld[k][4 * tq + 3], e0, e1, e2, e3);
+    y[tq] = bias4(e0);  // y[2*c + tq]: input c, time quad tq
+    y[2 + tq] = bias4(e1);
+    y[4 + tq] = bias4(e2);
+    y[6 + tq] = bias4(e3);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bad |= (y[2 * c + tq] - 0x11111111u) & ~y[2 * c + tq];
+  }
+
+  __device__ static void store_input(const uint32_t (&y)[8], uint8_t* st, int k, int c, uint32_t (&sy)[ITER][4],
+                                     uint32_t (&sw)[ITER][4], int tid) {
+    const int item = tid + k * NT;
+    const int q = item % QUADS, g = item / QUADS;
+    const int row = 4 * q + c;
+    const uint32_t ya = y[2 * c], yb = y[2 * c + 1];
+    const uint32_t ra = bre4(ya), ia = bim4(ya), rb = bre4(yb), ib = bim4(yb);
+    sy[k][c] = bytesum(yb, bytesum(ya, sy[k][c]));
+    sw[k][c] = bytesum(ib, bytesum(ia, sw[k][c]));
+    v4i v;
+    v.x = (int)ra;
+    v.y = (int)ia;
+    v.z = (int)rb;
+    v.w = (int)ib;
+    *reinterpret_cast<v4i*>(st + row * ROWB + ((g ^ swz(row)) << 4)) = v;
+  }
+
   template <int PH>
-  __device__ static void unpack_phase(const uint32_t (&ld)[D::ITER][8], uint32_t (&y)[D::ITER][8], uint8_t* st,
-                                      uint32_t (&sy)[D::ITER][4], uint32_t (&sw)[D::ITER][4], uint32_t& bad) {
-#pragma unroll
-    for (int k = 0; k < D::ITER; ++k) {
-      if (!has_item(k)) continue;
+  __device__ static void unpack_phase(const uint32_t (&ld)[ITER][8], uint32_t (&y)[8], uint8_t* st,
+                                      uint32_t (&sy)[ITER][4], uint32_t (&sw)[ITER][4], uint32_t& bad, int tid) {
+    if constexpr (ITER == 1) {
+      if (!has_item(tid, 0)) return;
       if constexpr (PH < 2) {
-        uint32_t e0, e1, e2, e3;
-        transpose4x4(ld[k][4 * PH], ld[k][4 * PH + 1], ld[k][4 * PH + 2], ld[k][4 * PH + 3], e0, e1, e2, e3);
-        // y[k][2*c + PH]: input c, time quad PH
-        y[k][PH] = bias4(e0);
-        y[k][2 + PH] = bias4(e1);
-        y[k][4 + PH] = bias4(e2);
-        y[k][6 + PH] = bias4(e3);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) bad |= (y[k][2 * c + PH] - 0x11111111u) & ~y[k][2 * c + PH];
+        transpose_tq(ld, y, 0, PH, bad);
       } else {
-        const int item = threadIdx.x + k * D::NT;
-        const int q = item % D::QUADS, g = item / D::QUADS;
+        store_input(y, st, 0, 2 * (PH - 2), sy, sw, tid);
+        store_input(y, st, 0, 2 * (PH - 2) + 1, sy, sw, tid);
+      }
+    } else {
+      constexpr int k = PH / 2;
+      if (!has_item(tid, k)) return;
+      if constexpr (PH % 2 == 0) {
+        transpose_tq(ld, y, k, 0, bad);
+        transpose_tq(ld, y, k, 1, bad);
+      } else {
 #pragma unroll
-        for (int cc = 0; cc < 2; ++cc) {
-          const int c = 2 * (PH - 2) + cc;
-          const int row = 4 * q + c;
-          const uint32_t ya = y[k][2 * c], yb = y[k][2 * c + 1];
-          const uint32_t ra = bre4(ya), ia = bim4(ya), rb = bre4(yb), ib = bim4(yb);
-          sy[k][c] = bytesum(yb, bytesum(ya, sy[k][c]));
-          sw[k][c] = bytesum(ib, bytesum(ia, sw[k][c]));
-          v4i v;
-          v.x = (int)ra;
-          v.y = (int)ia;
-          v.z = (int)rb;
-          v.w = (int)ib;
-          *reinterpret_cast<v4i*>(st + row * D::ROWB + ((g ^ swz(row)) << 4)) = v;
-        }
+        for (int c = 0; c < 4; ++c) store_input(y, st, k, c, sy, sw, tid);
       }
     }
   }
 
-  __device__ static void unpack_all(const uint32_t (&ld)[D::ITER][8], uint8_t* st, uint32_t (&sy)[D::ITER][4],
-                                    uint32_t (&sw)[D::ITER][4], uint32_t& bad) {
-    uint32_t y[D::ITER][8];
-    unpack_phase<0>(ld, y, st, sy, sw, bad);
-    unpack_phase<1>(ld, y, st, sy, sw, bad);
-    unpack_phase<2>(ld, y, st, sy, sw, bad);
-    unpack_phase<3>(ld, y, st, sy, sw, bad);
+  __device__ static void unpack_all(const uint32_t (&ld)[ITER][8], uint8_t* st, uint32_t (&sy)[ITER][4],
+                                    uint32_t (&sw)[ITER][4], uint32_t& bad, int tid) {
+    uint32_t y[8];
+    unpack_phase<0>(ld, y, st, sy, sw, bad, tid);
+    unpack_phase<1>(ld, y, st, sy, sw, bad, tid);
+    unpack_phase<2>(ld, y, st, sy, sw, bad, tid);
+    unpack_phase<3>(ld, y, st, sy, sw, bad, tid);
   }
 
   // Rare path: replace every invalid sample of a stage buffer (a biased part
   // of 0, i.e. the code 8) by a zero sample (u = w = 8) and correct the
-  // per-input sums.  All threads of the workgroup take part.
-  __device__ static void fixup_invalid(uint8_t* st, uint32_t* s_sy, uint32_t* s_sw) {
-    for (int gi = threadIdx.x; gi < NB * D::ROWB / 8; gi += D::NT) {
+  // per-input sums.
+  __device__ static void fixup_invalid(uint8_t* st, uint32_t* s_sy, uint32_t* s_sw, int tid) {
+    for (int gi = tid; gi < BYTES / 8; gi += NT) {
       uint2* gp = reinterpret_cast<uint2*>(st) + gi;
       uint2 v = *gp;
       const uint32_t ok = (v.x + 0x7F7F7F7Fu) & (v.y + 0x7F7F7F7Fu) & 0x80808080u;
       if (ok == 0x80808080u) continue;
-      const int row = (gi * 8) / D::ROWB;
+      const int row = (gi * 8) / ROWB;
       uint32_t dy = 0, dw = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
@@ -213,272 +229,556 @@ struct DiagUnit {
     }
   }
 
-  // End of an unpack: raise the workgroup flag of stage buffer `slot` if any
-  // lane saw an invalid code.
-  __device__ static void publish_bad(uint32_t bad, uint32_t* s_bad, int slot) {
-    if (__any((bad & 0x88888888u) != 0u) && (threadIdx.x & 63) == 0) s_bad[slot] = 1u;
+  // End of an unpack: raise the (workgroup-wide) flag of stage buffer `slot`
+  // if any lane saw an invalid code.
+  __device__ static void publish_bad(uint32_t bad, uint32_t* s_bad, int slot, int tid) {
+    if (__any((bad & 0x88888888u) != 0u) && (tid & 63) == 0) s_bad[slot] = 1u;
   }
 
   // After the barrier that ends an unpack: fix the stage buffer if flagged.
-  __device__ static void check_bad(uint8_t* st, uint32_t* s_bad, int slot, uint32_t* s_sy, uint32_t* s_sw) {
+  // The flag is shared by all thread groups of the workgroup, so every group
+  // takes the same branch and the barriers inside stay matched.
+  __device__ static void check_bad(uint8_t* st, uint32_t* s_bad, int slot, uint32_t* s_sy, uint32_t* s_sw, int tid) {
     if (s_bad[slot]) {
-      fixup_invalid(st, s_sy, s_sw);
+      fixup_invalid(st, s_sy, s_sw, tid);
       __syncthreads();
-      if (threadIdx.x == 0) s_bad[slot] = 0u;
+      if (tid == 0) s_bad[slot] = 0u;
+      __syncthreads();
     }
   }
 
   __device__ static v4i read_frag(const uint8_t* st, int row, int chunk) {
-    return *reinterpret_cast<const v4i*>(st + row * D::ROWB + ((chunk ^ swz(row)) << 4));
+    return *reinterpret_cast<const v4i*>(st + row * ROWB + ((chunk ^ swz(row)) << 4));
   }
 
-  __device__ static v4i to_b(v4i a) {
-    v4i b;
-    b.x = (int)op_s((uint32_t)a.x, (uint32_t)a.y);
-    b.y = (int)op_d((uint32_t)a.x, (uint32_t)a.y);
-    b.z = (int)op_s((uint32_t)a.z, (uint32_t)a.w);
-    b.w = (int)op_d((uint32_t)a.z, (uint32_t)a.w);
-    return b;
-  }
-
-  // One chunk of the main loop: the MFMAs of chunk c from its stage buffer,
-  // with the four unpack phases of chunk c+1 (held in `ld`) into the other
-  // stage buffer placed between the K-steps, and the loads of chunk c+2 issued
-  // once `ld` is consumed.  MORE1 / MORE2: chunks c+1 / c+2 exist.  Ends with a
-  // barrier (and the rare invalid-code fix-up of the new stage buffer).
-  template <bool ALIGNED, bool MORE1, bool MORE2>
-  __device__ static void chunk_step(const Problem& p, int f, int t0, int t1, int c, int64_t stride, uint8_t* lds,
-                                    int rrow, int crow, uint32_t (&ld)[D::ITER][8], v16i (&acc)[D::FM][D::FN],
-                                    uint32_t (&sy)[D::ITER][4], uint32_t (&sw)[D::ITER][4], uint32_t* s_bad,
-                                    uint32_t* s_sy, uint32_t* s_sw) {
-    const int half = (threadIdx.x & 63) >> 5;
-    const uint8_t* st = lds + (c & 1) * D::STAGE;
-    uint8_t* nst = lds + ((c + 1) & 1) * D::STAGE;
-    uint32_t bad = 0;
-    uint32_t y[D::ITER][8];
+  // Reduce the per-thread sums into s_sy / s_sw, then turn them into the
+  // correction terms e_k = Sy_k + 30 Sw_k and g_k = Sy_k - 2 Sw_k in place.
+  __device__ static void finish_sums(const uint32_t (&sy)[ITER][4], const uint32_t (&sw)[ITER][4], uint32_t* s_sy,
+                                     uint32_t* s_sw, int tid) {
 #pragma unroll
-    for (int ks = 0; ks < D::KSTEPS; ++ks) {
-      v4i a[D::FM], b[D::FN];
+    for (int k = 0; k < ITER; ++k) {
+      if (!has_item(tid, k)) continue;
+      const int q = (tid + k * NT) % QUADS;
 #pragma unroll
-      for (int x = 0; x < D::FM; ++x) a[x] = read_frag(st, rrow + 32 * x, 2 * ks + half);
-#pragma unroll
-      for (int x = 0; x < D::FN; ++x) b[x] = to_b(read_frag(st, crow + 32 * x, 2 * ks + half));
-#pragma unroll
-      for (int x = 0; x < D::FM; ++x)
-#pragma unroll
-        for (int z = 0; z < D::FN; ++z)
-          acc[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[x], b[z], acc[x][z], 0, 0, 0);
-      if constexpr (MORE1) {
-        if (ks == 0) unpack_phase<0>(ld, y, nst, sy, sw, bad);
-        if (ks == 1) unpack_phase<1>(ld, y, nst, sy, sw, bad);
-        if (ks == 2) unpack_phase<2>(ld, y, nst, sy, sw, bad);
-        if (ks == 3) unpack_phase<3>(ld, y, nst, sy, sw, bad);
-      }
-      if constexpr (MORE2) {
-        if (ks == 1) load_chunk<ALIGNED>(p, f, t0, t1, c + 2, stride, ld);
+      for (int cc = 0; cc < 4; ++cc) {
+        atomicAdd(&s_sy[4 * q + cc], sy[k][cc]);
+        atomicAdd(&s_sw[4 * q + cc], sw[k][cc]);
       }
     }
-    if constexpr (MORE1) publish_bad(bad, s_bad, (c + 1) & 1);
     __syncthreads();
-    if constexpr (MORE1) check_bad(nst, s_bad, (c + 1) & 1, s_sy, s_sw);
-  }
-
-  // Row (within a 32x32 tile) held by accumulator register r of this lane.
-  __device__ static int acc_row(int r, int lane) { return ((r >> 2) << 3) + ((lane >> 5) << 2) + (r & 3); }
-
-  // Write this wave's tile into an exchange area at column offset col0.
-  __device__ static void store_tile(int* xa, int col0, const v16i (&acc)[D::FM][D::FN], int lane) {
-#pragma unroll
-    for (int x = 0; x < D::FM; ++x)
-#pragma unroll
-      for (int z = 0; z < D::FN; ++z)
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-          xa[(32 * x + acc_row(r, lane)) * D::XPITCH + col0 + 32 * z + (lane & 31)] = acc[x][z][r];
-  }
-
-  // All threads: combine the quadrant of G_b at rows ib.., columns jb.. (in
-  // `own`) with its mirror quadrant at rows jb.., columns ib.. (in `mir`; the
-  // same area for a diagonal quadrant) and write the lower triangle into the
-  // accumulator.  s_e / s_g: per-input correction terms.  Eight elements per
-  // thread are in flight at a time, so read-modify-write latencies overlap.
-  __device__ static void combine(const Problem& p, int f, const int* own, const int* mir, int ib, int jb,
-                                 const int* s_e, const int* s_g, uint32_t tproc, int mode) {
-    constexpr int UN = 8;
-    const int64_t nb = tri_index(p.n_inputs, 0);
-    int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
-    for (int base = threadIdx.x; base < D::H * D::H; base += D::NT * UN) {
-      int2 val[UN];
-      int64_t pos[UN];
-      bool ok[UN];
-#pragma unroll
-      for (int u = 0; u < UN; ++u) {
-        const int idx = base + u * D::NT;
-        const int il = (idx / D::H) % D::H, jl = idx % D::H;
-        const int i = ib + il, j = jb + jl;
-        ok[u] = idx < D::H * D::H && i >= j && i < p.n_inputs;
-        const uint32_t gij = (uint32_t)own[il * D::XPITCH + jl];
-        const uint32_t gji = (uint32_t)mir[jl * D::XPITCH + il];
-        const int ii = min(i, NB - 1), jj = min(j, NB - 1);
-        const int re2 = (int)(gij + gji - (uint32_t)s_e[ii] - (uint32_t)s_e[jj] + 256u * tproc);
-        const int im2 = (int)(gji - gij + (uint32_t)s_g[ii] - (uint32_t)s_g[jj]);
-        val[u] = make_int2(re2 >> 1, im2 >> 1);
-        pos[u] = ok[u] ? tri_index(i, j) : 0;
-      }
-      if (mode == kWriteStore) {
-#pragma unroll
-        for (int u = 0; u < UN; ++u)
-          if (ok[u]) out[pos[u]] = val[u];
-      } else if (mode == kWriteAdd) {
-        int2 old[UN];
-#pragma unroll
-        for (int u = 0; u < UN; ++u) old[u] = out[pos[u]];
-#pragma unroll
-        for (int u = 0; u < UN; ++u)
-          if (ok[u]) out[pos[u]] = make_int2(old[u].x + val[u].x, old[u].y + val[u].y);
-      } else {
-#pragma unroll
-        for (int u = 0; u < UN; ++u)
-          if (ok[u]) {
-            __hip_atomic_fetch_add(&out[pos[u]].x, val[u].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&out[pos[u]].y, val[u].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-      }
+    for (int k = tid; k < ROWS; k += NT) {
+      const uint32_t y = s_sy[k], w = s_sw[k];
+      s_sy[k] = y + 30u * w;
+      s_sw[k] = y - 2u * w;
     }
+    __syncthreads();
   }
 };
 
-template <int NT>
-constexpr int diag_min_blocks = NT >= 512 ? 1 : 2;
+__device__ inline v4i to_b(v4i a) {
+  v4i b;
+  b.x = (int)op_s((uint32_t)a.x, (uint32_t)a.y);
+  b.y = (int)op_d((uint32_t)a.x, (uint32_t)a.y);
+  b.z = (int)op_s((uint32_t)a.z, (uint32_t)a.w);
+  b.w = (int)op_d((uint32_t)a.z, (uint32_t)a.w);
+  return b;
+}
 
-template <int NB, int TC, int WC, bool ALIGNED>
-__global__ __launch_bounds__(128 * WC, diag_min_blocks<128 * WC>) void xmac_diag_i8(Problem p, int nsplit,
-                                                                                  int tsplit, int mode) {
-  using D = Diag<NB, TC, WC>;
-  using U = DiagUnit<NB, TC, WC>;
-  static_assert(D::NT == 128 * WC, "thread count must match the launch bounds");
-  __shared__ __attribute__((aligned(16))) uint8_t lds[D::LDS];
-  __shared__ uint32_t s_sy[NB], s_sw[NB];
-  __shared__ uint32_t s_bad[2];
+// Row (within a 32x32 tile) held by accumulator register r of this lane.
+__device__ inline int acc_row(int r, int lane) { return ((r >> 2) << 3) + ((lane >> 5) << 2) + (r & 3); }
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// Both parts of a baseline from the two biased products (see the header):
+// 2 Re = G_b[i][j] + G_b[j][i] - e_i - e_j + 256 T,  2 Im = G_b[j][i] - G_b[i][j] + g_i - g_j.
+__device__ inline int2 baseline(uint32_t gij, uint32_t gji, uint32_t ei, uint32_t ej, uint32_t gi, uint32_t gj,
+                                uint32_t tproc) {
+  const int re2 = (int)(gij + gji - ei - ej + 256u * tproc);
+  const int im2 = (int)(gji - gij + gi - gj);
+  return make_int2(re2 >> 1, im2 >> 1);
+}
+
+// Write UN baselines per thread with one of the write modes; RMW loads are
+// all issued before any store so their latencies overlap.
+template <int UN>
+__device__ inline void write_out(int2* out, const int64_t (&pos)[UN], const bool (&ok)[UN], const int2 (&val)[UN],
+                                 int mode) {
+  if (mode == kWriteStore) {
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+      if (ok[u]) out[pos[u]] = val[u];
+  } else if (mode == kWriteAdd) {
+    int2 old[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) old[u] = out[ok[u] ? pos[u] : 0];
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+      if (ok[u]) out[pos[u]] = make_int2(old[u].x + val[u].x, old[u].y + val[u].y);
+  } else if (mode == kWriteAtomic) {
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+      if (ok[u]) {
+        __hip_atomic_fetch_add(&out[pos[u]].x, val[u].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&out[pos[u]].y, val[u].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+  }
+}
+
+// Main loop shared by all unit kinds: prologue (chunk 0 unpacked, chunk 1
+// loaded), then for every chunk the K-steps of the unit (kstep(st, ks)) with
+// the four unpack phases of the next chunk placed after them and the loads of
+// the chunk after that issued once the registers are free.
+template <class S, bool ALIGNED, class KStep>
+__device__ inline void run_chunks(const Problem& p, const typename S::Map& m, int f, int t0, int t1, int64_t stride,
+                                  int tid, uint8_t* lds, uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad,
+                                  uint32_t (&sy)[S::ITER][4], uint32_t (&sw)[S::ITER][4], int nchunks, KStep&& kstep) {
+  uint32_t ld[S::ITER][8];
+  if (nchunks > 0) {
+    uint32_t bad = 0;
+    S::template load<ALIGNED>(p, m, f, t0, t1, 0, stride, tid, ld);
+    S::unpack_all(ld, lds, sy, sw, bad, tid);
+    S::publish_bad(bad, s_bad, 0, tid);
+    if (nchunks > 1) S::template load<ALIGNED>(p, m, f, t0, t1, 1, stride, tid, ld);
+  }
+  __syncthreads();
+  if (nchunks > 0) S::check_bad(lds, s_bad, 0, s_sy, s_sw, tid);
+
+  auto step = [&](int c, auto more1, auto more2) {
+    constexpr bool M1 = decltype(more1)::value, M2 = decltype(more2)::value;
+    const uint8_t* st = lds + (c & 1) * S::BYTES;
+    uint8_t* nst = lds + ((c + 1) & 1) * S::BYTES;
+    uint32_t bad = 0;
+    uint32_t y[8];
+#pragma unroll
+    for (int ks = 0; ks < S::KSTEPS; ++ks) {
+      kstep(st, ks);
+      if constexpr (M1) {
+        if (ks == 0) S::template unpack_phase<0>(ld, y, nst, sy, sw, bad, tid);
+        if (ks == 1) S::template unpack_phase<1>(ld, y, nst, sy, sw, bad, tid);
+        if (ks == 2) S::template unpack_phase<2>(ld, y, nst, sy, sw, bad, tid);
+        if (ks == 3) S::template unpack_phase<3>(ld, y, nst, sy, sw, bad, tid);
+      }
+      if constexpr (M2) {
+        if (ks == S::LOAD_PHASE) S::template load<ALIGNED>(p, m, f, t0, t1, c + 2, stride, tid, ld);
+      }
+    }
+    if constexpr (M1) S::publish_bad(bad, s_bad, (c + 1) & 1, tid);
+    __syncthreads();
+    if constexpr (M1) S::check_bad(nst, s_bad, (c + 1) & 1, s_sy, s_sw, tid);
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  int c = 0;
+  for (; c + 2 < nchunks; ++c) step(c, T_{}, T_{});
+  if (c + 1 < nchunks) {
+    step(c, T_{}, F_{});
+    ++c;
+  }
+  if (c < nchunks) step(c, F_{}, F_{});
+}
+
+// ---- diagonal unit -----------------------------------------------------------
+
+template <int NB, int WC>
+struct DiagGeom {
+  static constexpr int WR = 2;                       // wave rows
+  static constexpr int NW = WR * WC;                 // waves
+  static constexpr int NT = 64 * NW;                 // threads
+  static constexpr int TM = NB / WR;                 // wave tile rows
+  static constexpr int TN = NB / WC;                 // wave tile columns
+  static constexpr int FM = TM / 32;                 // 32x32 MFMA tiles along rows
+  static constexpr int FN = TN / 32;                 // ... along columns
+  static constexpr int H = NB / 2;                   // quadrant side
+  static constexpr int XPITCH = H + 1;
+  static constexpr int XAREA = H * XPITCH;           // int32 words of one exchange area
+  static constexpr int STAGE = NB * 128;             // one stage buffer (TC = 64)
+  static constexpr int LDS = (2 * STAGE > 2 * XAREA * 4) ? 2 * STAGE : 2 * XAREA * 4;
+  static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tiles are made of 32x32 MFMA tiles");
+  static_assert(WC % 2 == 0, "quadrants are made of whole wave tiles");
+};
+
+// Write this wave's tile into an exchange area at column offset col0.
+template <class G>
+__device__ inline void store_tile(int* xa, int col0, const v16i (&acc)[G::FM][G::FN], int lane) {
+#pragma unroll
+  for (int x = 0; x < G::FM; ++x)
+#pragma unroll
+    for (int z = 0; z < G::FN; ++z)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        xa[(32 * x + acc_row(r, lane)) * G::XPITCH + col0 + 32 * z + (lane & 31)] = acc[x][z][r];
+}
+
+// Combine the quadrant of G_b at local rows ib.., columns jb.. (in `own`) with
+// its mirror quadrant (in `mir`; the same area for a diagonal quadrant) and
+// write the lower triangle; local row r is input ibase + r.
+template <class G>
+__device__ inline void combine_quadrant(const Problem& p, int f, int ibase, const int* own, const int* mir, int ib,
+                                        int jb, const uint32_t* s_e, const uint32_t* s_g, uint32_t tproc, int mode,
+                                        int tid) {
+  constexpr int UN = 8;
+  const int64_t nb = tri_index(p.n_inputs, 0);
+  int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
+  for (int base = tid; base < G::H * G::H; base += G::NT * UN) {
+    int2 val[UN];
+    int64_t pos[UN];
+    bool ok[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int idx = base + u * G::NT;
+      const int il = (idx / G::H) % G::H, jl = idx % G::H;
+      const int li = ib + il, lj = jb + jl;
+      const int i = ibase + li, j = ibase + lj;
+      ok[u] = idx < G::H * G::H && li >= lj && i < p.n_inputs;
+      val[u] = baseline((uint32_t)own[il * G::XPITCH + jl], (uint32_t)mir[jl * G::XPITCH + il], s_e[li], s_e[lj],
+                        s_g[li], s_g[lj], tproc);
+      pos[u] = tri_index(i, j);
+    }
+    write_out<UN>(out, pos, ok, val, mode);
+  }
+}
+
+// One diagonal unit: inputs ibase .. ibase+NB-1 of channel f over samples
+// [t0, t1), run by the NT threads whose local index is tid.  lds: G::LDS
+// bytes; s_sy, s_sw: NB words each; s_bad: 2 words shared by the workgroup.
+template <int NB, int WC, bool ALIGNED>
+__device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int tid, uint8_t* lds, uint32_t* s_sy,
+                         uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  using G = DiagGeom<NB, WC>;
+  using S = Stage<NB, 64, G::NT>;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WC, wc = wave % WC;
-  const int u = xcd_remap(blockIdx.x, gridDim.x);
-  const int f = u / nsplit, sp = u % nsplit;
-  const int t0 = sp * tsplit;
-  const int t1 = min(p.n_time, t0 + tsplit);
-  const int nchunks = t1 > t0 ? (t1 - t0 + TC - 1) / TC : 0;
+  const int nchunks = t1 > t0 ? (t1 - t0 + 63) / 64 : 0;
   const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
 
-  for (int k = tid; k < NB; k += D::NT) {
+  for (int k = tid; k < NB; k += G::NT) {
     s_sy[k] = 0;
     s_sw[k] = 0;
   }
   if (tid < 2) s_bad[tid] = 0;
   __syncthreads();
 
-  v16i acc[D::FM][D::FN];
+  v16i acc[G::FM][G::FN];
 #pragma unroll
-  for (int x = 0; x < D::FM; ++x)
+  for (int x = 0; x < G::FM; ++x)
 #pragma unroll
-    for (int z = 0; z < D::FN; ++z) acc[x][z] = v16i{0};
-  uint32_t sy[D::ITER][4], sw[D::ITER][4];
+    for (int z = 0; z < G::FN; ++z) acc[x][z] = v16i{0};
+  uint32_t sy[S::ITER][4], sw[S::ITER][4];
 #pragma unroll
-  for (int k = 0; k < D::ITER; ++k)
+  for (int k = 0; k < S::ITER; ++k)
 #pragma unroll
     for (int c = 0; c < 4; ++c) sy[k][c] = sw[k][c] = 0;
 
-  uint32_t ld[D::ITER][8];
-  if (nchunks > 0) {
-    uint32_t bad = 0;
-    U::template load_chunk<ALIGNED>(p, f, t0, t1, 0, stride, ld);
-    U::unpack_all(ld, lds, sy, sw, bad);
-    U::publish_bad(bad, s_bad, 0);
-    if (nchunks > 1) U::template load_chunk<ALIGNED>(p, f, t0, t1, 1, stride, ld);
-  }
-  __syncthreads();
-  if (nchunks > 0) U::check_bad(lds, s_bad, 0, s_sy, s_sw);
-
-  const int rrow = wr * D::TM + (lane & 31), crow = wc * D::TN + (lane & 31);
-  int c = 0;
-  for (; c + 2 < nchunks; ++c)
-    U::template chunk_step<ALIGNED, true, true>(p, f, t0, t1, c, stride, lds, rrow, crow, ld, acc, sy, sw, s_bad,
-                                                s_sy, s_sw);
-  if (c + 1 < nchunks) {
-    U::template chunk_step<ALIGNED, true, false>(p, f, t0, t1, c, stride, lds, rrow, crow, ld, acc, sy, sw, s_bad,
-                                                 s_sy, s_sw);
-    ++c;
-  }
-  if (c < nchunks)
-    U::template chunk_step<ALIGNED, false, false>(p, f, t0, t1, c, stride, lds, rrow, crow, ld, acc, sy, sw, s_bad,
-                                                  s_sy, s_sw);
-
-  // Per-input sums of this unit, then the correction terms
-  // e_k = Sy_k + 30 Sw_k and g_k = Sy_k - 2 Sw_k (in place).
+  const int half = lane >> 5;
+  const int rrow = wr * G::TM + (lane & 31), crow = wc * G::TN + (lane & 31);
+  const typename S::Map m{ibase, NB / 4, ibase};
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, s_bad, sy, sw, nchunks,
+                         [&](const uint8_t* st, int ks) {
+                           v4i a[G::FM], b[G::FN];
 #pragma unroll
-  for (int k = 0; k < D::ITER; ++k) {
-    if (!U::has_item(k)) continue;
-    const int q = (tid + k * D::NT) % D::QUADS;
+                           for (int x = 0; x < G::FM; ++x) a[x] = S::read_frag(st, rrow + 32 * x, 2 * ks + half);
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      atomicAdd(&s_sy[4 * q + cc], sy[k][cc]);
-      atomicAdd(&s_sw[4 * q + cc], sw[k][cc]);
-    }
-  }
-  __syncthreads();
-  for (int k = tid; k < NB; k += D::NT) {
-    const uint32_t y = s_sy[k], w = s_sw[k];
-    s_sy[k] = y + 30u * w;
-    s_sw[k] = y - 2u * w;
-  }
-  __syncthreads();
-  const int* s_e = reinterpret_cast<const int*>(s_sy);
-  const int* s_g = reinterpret_cast<const int*>(s_sw);
+                           for (int x = 0; x < G::FN; ++x)
+                             b[x] = to_b(S::read_frag(st, crow + 32 * x, 2 * ks + half));
+#pragma unroll
+                           for (int x = 0; x < G::FM; ++x)
+#pragma unroll
+                             for (int z = 0; z < G::FN; ++z)
+                               acc[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[x], b[z], acc[x][z], 0, 0, 0);
+                         });
 
-  const uint32_t tproc = (uint32_t)(nchunks * TC);
-  const int wmode = nsplit > 1 ? kWriteAtomic : mode;
+  S::finish_sums(sy, sw, s_sy, s_sw, tid);
+  const uint32_t tproc = (uint32_t)(nchunks * 64);
   int* xa = reinterpret_cast<int*>(lds);
-  int* xb = xa + D::XAREA;
+  int* xb = xa + G::XAREA;
   constexpr int HW = WC / 2;  // wave columns per quadrant
   // Round 1: quadrant (1,0) against its mirror (0,1).
-  if (wr == 0 && wc >= HW) U::store_tile(xa, (wc - HW) * D::TN, acc, lane);
-  if (wr == 1 && wc < HW) U::store_tile(xb, wc * D::TN, acc, lane);
+  if (wr == 0 && wc >= HW) store_tile<G>(xa, (wc - HW) * G::TN, acc, lane);
+  if (wr == 1 && wc < HW) store_tile<G>(xb, wc * G::TN, acc, lane);
   __syncthreads();
-  U::combine(p, f, xb, xa, D::H, 0, s_e, s_g, tproc, wmode);
+  combine_quadrant<G>(p, f, ibase, xb, xa, G::H, 0, s_sy, s_sw, tproc, mode, tid);
   __syncthreads();
   // Round 2: the diagonal quadrants (0,0) and (1,1), each against itself.
-  if (wr == 0 && wc < HW) U::store_tile(xa, wc * D::TN, acc, lane);
-  if (wr == 1 && wc >= HW) U::store_tile(xb, (wc - HW) * D::TN, acc, lane);
+  if (wr == 0 && wc < HW) store_tile<G>(xa, wc * G::TN, acc, lane);
+  if (wr == 1 && wc >= HW) store_tile<G>(xb, (wc - HW) * G::TN, acc, lane);
   __syncthreads();
-  U::combine(p, f, xa, xa, 0, 0, s_e, s_g, tproc, wmode);
-  U::combine(p, f, xb, xb, D::H, D::H, s_e, s_g, tproc, wmode);
+  combine_quadrant<G>(p, f, ibase, xa, xa, 0, 0, s_sy, s_sw, tproc, mode, tid);
+  combine_quadrant<G>(p, f, ibase, xb, xb, G::H, G::H, s_sy, s_sw, tproc, mode, tid);
+  __syncthreads();
 }
 
-template <int NB, int TC, int WC>
-static int launch_diag(const Problem& p, int nsplit, int mode, hipStream_t s) {
-  using D = Diag<NB, TC, WC>;
-  const int tsplit = (p.n_time + nsplit - 1) / nsplit;
-  const int64_t grid = (int64_t)p.n_chan * nsplit;
-  if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
+// ---- pair unit ----------------------------------------------------------------
+
+// Rows I0 .. I0+127 against columns J0 .. J0+255 (all j < i), 8 waves as 2 x 4
+// tiles of 64 x 64, each holding both products (C1 = A_I B_J^T, Hm = B_I A_J^T).
+struct PairGeom {
+  static constexpr int NT = 512;
+  static constexpr int ROWS = 384;                   // stage rows: 128 of I, then 256 of J
+  static constexpr int LDS = 2 * ROWS * 128;
+};
+
+template <bool ALIGNED>
+__device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1, int tid, uint8_t* lds,
+                         uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  using S = Stage<PairGeom::ROWS, 64, PairGeom::NT>;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / 4, wc = wave % 4;
+  const int nchunks = t1 > t0 ? (t1 - t0 + 63) / 64 : 0;
   const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
-  const bool aligned = (p.n_inputs % 4 == 0) && ((reinterpret_cast<uintptr_t>(p.in) & 3) == 0) &&
-                       (int64_t)TC * stride + p.n_inputs < 0x7FFFFFFF;
-  if (aligned)
-    hipLaunchKernelGGL((xmac_diag_i8<NB, TC, WC, true>), dim3((unsigned)grid), dim3(D::NT), 0, s, p, nsplit,
+
+  for (int k = tid; k < PairGeom::ROWS; k += PairGeom::NT) {
+    s_sy[k] = 0;
+    s_sw[k] = 0;
+  }
+  if (tid < 2) s_bad[tid] = 0;
+  __syncthreads();
+
+  v16i c1[2][2], hm[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) c1[x][z] = hm[x][z] = v16i{0};
+  uint32_t sy[S::ITER][4], sw[S::ITER][4];
+#pragma unroll
+  for (int k = 0; k < S::ITER; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sy[k][c] = sw[k][c] = 0;
+
+  const int half = lane >> 5;
+  const int irow = wr * 64 + (lane & 31), jrow = 128 + wc * 64 + (lane & 31);
+  const typename S::Map m{I0, 32, J0};
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, s_bad, sy, sw, nchunks,
+                         [&](const uint8_t* st, int ks) {
+                           v4i ai[2], bi[2], aj[2], bj[2];
+#pragma unroll
+                           for (int x = 0; x < 2; ++x) {
+                             ai[x] = S::read_frag(st, irow + 32 * x, 2 * ks + half);
+                             aj[x] = S::read_frag(st, jrow + 32 * x, 2 * ks + half);
+                           }
+#pragma unroll
+                           for (int x = 0; x < 2; ++x) {
+                             bi[x] = to_b(ai[x]);
+                             bj[x] = to_b(aj[x]);
+                           }
+#pragma unroll
+                           for (int x = 0; x < 2; ++x)
+#pragma unroll
+                             for (int z = 0; z < 2; ++z) {
+                               c1[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai[x], bj[z], c1[x][z], 0, 0, 0);
+                               hm[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bi[x], aj[z], hm[x][z], 0, 0, 0);
+                             }
+                         });
+
+  S::finish_sums(sy, sw, s_sy, s_sw, tid);
+  const uint32_t tproc = (uint32_t)(nchunks * 64);
+  const int64_t nb = tri_index(p.n_inputs, 0);
+  int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int rh = 0; rh < 2; ++rh) {
+        int2 val[8];
+        int64_t pos[8];
+        bool ok[8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) {
+          const int r = 8 * rh + rr;
+          const int li = wr * 64 + 32 * x + acc_row(r, lane);  // stage row of i
+          const int lj = 128 + wc * 64 + 32 * z + (lane & 31);  // stage row of j
+          const int i = I0 + li, j = J0 + (lj - 128);
+          ok[rr] = i < p.n_inputs;
+          val[rr] = baseline((uint32_t)c1[x][z][r], (uint32_t)hm[x][z][r], s_sy[li], s_sy[lj], s_sw[li], s_sw[lj],
+                             tproc);
+          pos[rr] = tri_index(i, j);
+        }
+        write_out<8>(out, pos, ok, val, mode);
+      }
+  __syncthreads();
+}
+
+// ---- standalone grids -----------------------------------------------------------
+
+// Map the hardware workgroup id so that consecutive logical units land on the
+// same XCD (ids are dealt round-robin over 8 XCDs): neighbouring channels then
+// share an L2.
+__device__ inline int xcd_remap(int b, int n) {
+  if (n % 8) return b;
+  return (b % 8) * (n / 8) + b / 8;
+}
+
+template <int NT>
+constexpr int unit_min_blocks = NT >= 512 ? 1 : 2;
+
+// Diagonal units: unit id -> (channel, diagonal block, time split).
+template <int NB, int WC, bool ALIGNED>
+__global__ __launch_bounds__(128 * WC, unit_min_blocks<128 * WC>) void xmac_diag_i8(Problem p, int nblk, int nsplit,
+                                                                                  int tsplit, int mode) {
+  using G = DiagGeom<NB, WC>;
+  static_assert(G::NT == 128 * WC, "thread count must match the launch bounds");
+  __shared__ __attribute__((aligned(16))) uint8_t lds[G::LDS];
+  __shared__ uint32_t s_sy[NB], s_sw[NB], s_bad[2];
+  int u = xcd_remap(blockIdx.x, gridDim.x);
+  const int sp = u % nsplit;
+  u /= nsplit;
+  const int blk = u % nblk, f = u / nblk;
+  const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
+  run_diag<NB, WC, ALIGNED>(p, f, blk * NB, t0, t1, threadIdx.x, lds, s_sy, s_sw, s_bad,
+                            nsplit > 1 ? (int)kWriteAtomic : mode);
+}
+
+// Pair units: unit id -> (channel, (block pair, half), time split).
+__device__ inline void pair_decode(int pu, int& I0, int& J0) {
+  const int half = pu & 1, pr = pu >> 1;  // pr -> (bi, bj), bi > bj, row-major
+  int bi = (int)((sqrtf(8.0f * pr + 1.0f) + 1.0f) * 0.5f);
+  while (bi * (bi - 1) / 2 > pr) --bi;
+  while ((bi + 1) * bi / 2 <= pr) ++bi;
+  const int bj = pr - bi * (bi - 1) / 2;
+  I0 = 256 * bi + 128 * half;
+  J0 = 256 * bj;
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(512, 1) void xmac_pair_i8(Problem p, int npair, int nsplit, int tsplit, int mode) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[PairGeom::LDS];
+  __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS], s_bad[2];
+  int u = xcd_remap(blockIdx.x, gridDim.x);
+  const int sp = u % nsplit;
+  u /= nsplit;
+  const int pu = u % npair, f = u / npair;
+  int I0, J0;
+  pair_decode(pu, I0, J0);
+  const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
+  run_pair<ALIGNED>(p, f, I0, J0, t0, t1, threadIdx.x, lds, s_sy, s_sw, s_bad, nsplit > 1 ? (int)kWriteAtomic : mode);
+}
+
+static bool aligned_problem(const Problem& p) {
+  const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
+  return (p.n_inputs % 4 == 0) && ((reinterpret_cast<uintptr_t>(p.in) & 3) == 0) &&
+         64 * stride + p.n_inputs < 0x7FFFFFFF;
+}
+
+template <int NB, int WC>
+static int launch_diag(const Problem& p, int nblk, int nsplit, int mode, hipStream_t s) {
+  using G = DiagGeom<NB, WC>;
+  const int tsplit = (p.n_time + nsplit - 1) / nsplit;
+  const int64_t grid = (int64_t)p.n_chan * nblk * nsplit;
+  if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
+  if (aligned_problem(p))
+    hipLaunchKernelGGL((xmac_diag_i8<NB, WC, true>), dim3((unsigned)grid), dim3(G::NT), 0, s, p, nblk, nsplit,
                        tsplit, mode);
   else
-    hipLaunchKernelGGL((xmac_diag_i8<NB, TC, WC, false>), dim3((unsigned)grid), dim3(D::NT), 0, s, p, nsplit,
+    hipLaunchKernelGGL((xmac_diag_i8<NB, WC, false>), dim3((unsigned)grid), dim3(G::NT), 0, s, p, nblk, nsplit,
                        tsplit, mode);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
+}
+
+static int launch_pair(const Problem& p, int npair, int nsplit, int mode, hipStream_t s) {
+  const int tsplit = (p.n_time + nsplit - 1) / nsplit;
+  const int64_t grid = (int64_t)p.n_chan * npair * nsplit;
+  if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
+  if (aligned_problem(p))
+    hipLaunchKernelGGL((xmac_pair_i8<true>), dim3((unsigned)grid), dim3(PairGeom::NT), 0, s, p, npair, nsplit, tsplit,
+                       mode);
+  else
+    hipLaunchKernelGGL((xmac_pair_i8<false>), dim3((unsigned)grid), dim3(PairGeom::NT), 0, s, p, npair, nsplit, tsplit,
+                       mode);
+  return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
+}
+
+int mfma_units_per_channel(int n_inputs) {
+  if (n_inputs <= 256) return 1;
+  const int nb = (n_inputs + 255) / 256;
+  return nb + nb * (nb - 1);
 }
 
 int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, hipStream_t s) {
   if (engine != CORRX_ENGINE_MFMA_I8) return CORRX_EUNSUPPORTED;
   (void)tile_cfg;
-  if (p.n_inputs <= 64) return launch_diag<64, 64, 2>(p, nsplit, mode, s);
-  if (p.n_inputs <= 128) return launch_diag<128, 64, 2>(p, nsplit, mode, s);
-  if (p.n_inputs <= 256) return launch_diag<256, 64, 4>(p, nsplit, mode, s);
-  return CORRX_EUNSUPPORTED;
+  if (p.n_inputs <= 64) return launch_diag<64, 2>(p, 1, nsplit, mode, s);
+  if (p.n_inputs <= 128) return launch_diag<128, 2>(p, 1, nsplit, mode, s);
+  const int nb = (p.n_inputs + 255) / 256;
+  int rc = launch_diag<256, 4>(p, nb, nsplit, mode, s);
+  if (rc == CORRX_OK && nb > 1) rc = launch_pair(p, nb * (nb - 1), nsplit, mode, s);
+  return rc;
+}
+
+// ---- persistent batch kernel ----------------------------------------------------
+
+constexpr int kBatchLds =
+    DiagGeom<256, 4>::LDS > PairGeom::LDS ? DiagGeom<256, 4>::LDS : PairGeom::LDS;
+static_assert(2 * DiagGeom<128, 2>::LDS <= kBatchLds, "two 128-input units fit side by side");
+
+// Each unit kind of the batch kernel in its own function, so that each gets
+// its own register allocation.
+__device__ __noinline__ void batch_diag256(const Problem& p, int f, int blk, int t0, int t1, int tid, uint8_t* lds,
+                                           uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  run_diag<256, 4, true>(p, f, blk * 256, t0, t1, tid, lds, s_sy, s_sw, s_bad, mode);
+}
+__device__ __noinline__ void batch_pair(const Problem& p, int f, int pu, int t0, int t1, int tid, uint8_t* lds,
+                                        uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  int I0, J0;
+  pair_decode(pu, I0, J0);
+  run_pair<true>(p, f, I0, J0, t0, t1, tid, lds, s_sy, s_sw, s_bad, mode);
+}
+template <int NB>
+__device__ __noinline__ void batch_small_x2(const Problem& p, int f0, int t0, int t1, int tid, uint8_t* lds,
+                                            uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  const int g = tid >> 8, f = f0 + g;
+  run_diag<NB, 2, true>(p, min(f, p.n_chan - 1), 0, t0, t1, tid & 255, lds + g * DiagGeom<NB, 2>::LDS, s_sy + NB * g,
+                        s_sw + NB * g, s_bad, f < p.n_chan ? mode : (int)kWriteNone);
+}
+
+// One workgroup per compute unit pulls work items from a device counter until
+// the list is exhausted.  Every item is one unit (or two small units side by
+// side, on channels f and f+1 of the same array).  All arrays must be aligned.
+__global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const WorkItem* items, int n_items,
+                                                         int* counter) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kBatchLds];
+  __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS], s_bad[2];
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    // The item is the same for every lane: keep it in scalar registers.
+    const int iu = __builtin_amdgcn_readfirstlane(it);
+    WorkItem w;
+    w.array = __builtin_amdgcn_readfirstlane(items[iu].array);
+    w.channel = __builtin_amdgcn_readfirstlane(items[iu].channel);
+    w.tile = __builtin_amdgcn_readfirstlane(items[iu].tile);
+    w.t0 = __builtin_amdgcn_readfirstlane(items[iu].t0);
+    w.t1 = __builtin_amdgcn_readfirstlane(items[iu].t1);
+    w.kind = __builtin_amdgcn_readfirstlane(items[iu].kind);
+    w.atomic = __builtin_amdgcn_readfirstlane(items[iu].atomic);
+    const Problem p = args.arrays[w.array];
+    const int mode = w.atomic ? (int)kWriteAtomic : (int)kWriteAdd;
+    switch (w.kind) {
+      case kUnitDiag256:
+        batch_diag256(p, w.channel, w.tile, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
+        break;
+      case kUnitPair:
+        batch_pair(p, w.channel, w.tile, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
+        break;
+      case kUnitDiag128x2:
+        batch_small_x2<128>(p, w.channel, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
+        break;
+      default:  // kUnitDiag64x2
+        batch_small_x2<64>(p, w.channel, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
+        break;
+    }
+  }
+}
+
+__global__ void reset_counter(int* counter) { *counter = 0; }
+
+int launch_batch(const BatchArgs& args, const WorkItem* d_items, int n_items, int* d_counter, int grid,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, d_counter);
+  hipLaunchKernelGGL(xmac_batch_i8, dim3(grid), dim3(512), 0, s, args, d_items, n_items, d_counter);
+  return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
 }  // namespace corrx

@@ -66,6 +66,21 @@ def test_input_counts(cx, oracle_lib, engine, n):
 
 
 @pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n", [257, 300, 384, 511, 512, 513, 700, 1024])
+def test_multi_block_input_counts(cx, oracle_lib, engine, n):
+    # more than 256 inputs: diagonal blocks plus pair units
+    fc, tc = 2, 77
+    buf = synth.make_input(8000 + n, n, fc, tc)
+    _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} N={n}")
+
+
+def test_multi_block_split_and_layout(cx, oracle_lib):
+    n, fc, tc = 520, 1, 3000
+    buf = synth.make_input(8100, n, fc, tc, layout=1)
+    _compare(_run(cx, buf, n, fc, tc, layout=1), oracle_lib.xmac(buf, n, fc, tc, 1), n, "N=520 FTI split")
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("tc", [1, 15, 16, 63, 64, 65, 129, 1000, 4097])
 def test_ragged_time(cx, oracle_lib, engine, tc):
     n, fc = 256, 2
@@ -183,3 +198,61 @@ def test_beam(cx, oracle_lib):
     out = c.beam(torch.from_numpy(buf).cuda()).cpu().numpy()
     assert np.array_equal(out.astype(np.int64), oracle_lib.incoherent_beam(buf, n, fc, tc))
     c.close()
+
+
+BATCH = [(64, 6, 300, 0), (256, 3, 200, 0), (512, 2, 150, 0), (1024, 1, 70, 1), (128, 5, 333, 1), (100, 3, 90, 0)]
+
+
+def _batch_inputs(descs):
+    return [synth.make_input(9000 + k, n, f, t, layout=lay) for k, (n, f, t, lay) in enumerate(descs)]
+
+
+@pytest.mark.parametrize("tile_cfg", [None, "unit256", "splits"])
+def test_batch_uneven_arrays(cx, oracle_lib, tile_cfg):
+    import torch
+
+    descs = BATCH
+    bufs = _batch_inputs(descs)
+    cfg = None
+    if tile_cfg == "unit256":
+        cfg = [cx.CORRX_TILE_UNIT256] * len(descs)
+    elif tile_cfg == "splits":
+        cfg = [cx.CORRX_TILE_DEFAULT | (3 << 8)] * len(descs)
+    b = cx.Batch(descs, tile_cfg=cfg)
+    assert b.items > 0
+    ins = [torch.from_numpy(x).cuda() for x in bufs]
+    accs = b.new_accs()
+    b.xmac(ins, accs)
+    b.xmac(ins, accs)  # accumulates
+    torch.cuda.synchronize()
+    for (n, f, t, lay), x, acc in zip(descs, bufs, accs):
+        _compare(acc.cpu().numpy().astype(np.int64), 2 * oracle_lib.xmac(x, n, f, t, lay), n, f"batch N={n}")
+    b.close()
+
+
+def test_batch_matches_single_calls(cx):
+    import torch
+
+    descs = [(64, 9, 500, 0), (256, 4, 1000, 0), (512, 2, 600, 0)]
+    bufs = _batch_inputs(descs)
+    ins = [torch.from_numpy(x).cuda() for x in bufs]
+    b = cx.Batch(descs)
+    accs = b.new_accs()
+    b.xmac(ins, accs)
+    for (n, f, t, lay), x, acc in zip(descs, ins, accs):
+        c = cx.Correlator(n, f, t, lay)
+        ref = c.new_acc()
+        c.zero(ref)
+        c.xmac(x, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, acc)
+        c.close()
+    b.close()
+
+
+def test_batch_rejects_unaligned_inputs(cx):
+    with pytest.raises(cx.CorrxError) as e:
+        cx.Batch([(66, 2, 10, 0)])
+    assert e.value.status == cx.CORRX_EUNSUPPORTED
+    with pytest.raises(cx.CorrxError):
+        cx.Batch([(256, 2, 10, 0)], tile_cfg=[cx.CORRX_TILE_UNIT64])
