@@ -35,12 +35,12 @@ int resolve_engine(int e) { return e == CORRX_ENGINE_AUTO ? CORRX_ENGINE_MFMA_I8
 
 // Time splits per channel: enough work units to fill the chip (about two per
 // compute unit), at least 512 samples per split, at most kMaxUnitTime.
-int plan_splits(int n_chan, int units_per_chan, int n_time, int n_cu) {
+int plan_splits(int n_chan, int units_per_chan, int n_time, int n_cu, int max_unit = kMaxUnitTime) {
   const int64_t units = (int64_t)n_chan * units_per_chan;
   int split = 1;
   const int64_t target = 2LL * n_cu;
   while (units * split < target && n_time / (2 * split) >= 512) split *= 2;
-  while ((n_time + split - 1) / split > kMaxUnitTime) ++split;
+  while ((n_time + split - 1) / split > max_unit) ++split;
   return split;
 }
 
@@ -152,8 +152,10 @@ int corr_xmac(corrx_t h, const void* in, void* acc, void* stream) {
     rc = launch_plain(p, plan_splits(h->n_chan, nbk * (nbk + 1) / 2, h->n_time, h->n_cu), mode,
                       as_stream(stream));
   } else {
-    rc = launch_mfma(p, engine, plan_splits(h->n_chan, mfma_units_per_channel(h->n_inputs), h->n_time, h->n_cu),
-                     mode, CORRX_TILE_DEFAULT, as_stream(stream));
+    const int units = engine == CORRX_ENGINE_MFMA_F8 ? 1 : mfma_units_per_channel(h->n_inputs);
+    const int max_unit = engine == CORRX_ENGINE_MFMA_F8 ? kMaxUnitTimeF8 : kMaxUnitTime;
+    rc = launch_mfma(p, engine, plan_splits(h->n_chan, units, h->n_time, h->n_cu, max_unit), mode,
+                     CORRX_TILE_DEFAULT, as_stream(stream));
   }
   if (rc == CORRX_OK) h->samples += h->n_time;
   return rc;

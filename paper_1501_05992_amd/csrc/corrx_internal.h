@@ -21,6 +21,9 @@ constexpr int kBufferRsrcWord3 = 0x00020000;
 // Largest time range one work unit integrates.  Bounds the biased int32 sums
 // of the MFMA engines (|G_b| <= 900 per sample) well inside int32.
 constexpr int kMaxUnitTime = 1 << 20;
+// Same for the fp8 engine: fp32 partial sums stay exact integers while
+// 98 * samples <= 2^24; 2^17 samples keep a margin.
+constexpr int kMaxUnitTimeF8 = 1 << 17;
 
 // int32 bound of the accumulator: |Re|, |Im| <= 2 * 7 * 7 = 98 per sample.
 constexpr int64_t kMaxAccSamples = 21913098;  // floor((2^31 - 1) / 98)

@@ -66,6 +66,7 @@ struct Stage {
   static constexpr int BYTES = ROWS * ROWB;          // one stage buffer
   static constexpr int KSTEPS = TC / 16;             // K=32 (16-sample) MFMA steps per chunk
   static_assert(KSTEPS == 4 && ROWB == 128, "the unpack is split into four phases over 8 chunks per row");
+  static constexpr bool FP8 = false;
 
   // Stage quad q -> first input: the first `split` quads start at base0, the
   // rest at base1.
@@ -350,14 +351,16 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
 #pragma unroll
     for (int ks = 0; ks < S::KSTEPS; ++ks) {
       kstep(st, ks);
+      // unpack phase PH runs after K-step PH * KSTEPS / 4
       if constexpr (M1) {
-        if (ks == 0) S::template unpack_phase<0>(ld, y, nst, sy, sw, bad, tid);
-        if (ks == 1) S::template unpack_phase<1>(ld, y, nst, sy, sw, bad, tid);
-        if (ks == 2) S::template unpack_phase<2>(ld, y, nst, sy, sw, bad, tid);
-        if (ks == 3) S::template unpack_phase<3>(ld, y, nst, sy, sw, bad, tid);
+        if (ks == 0 * S::KSTEPS / 4) S::template unpack_phase<0>(ld, y, nst, sy, sw, bad, tid);
+        if (ks == 1 * S::KSTEPS / 4) S::template unpack_phase<1>(ld, y, nst, sy, sw, bad, tid);
+        if (ks == 2 * S::KSTEPS / 4) S::template unpack_phase<2>(ld, y, nst, sy, sw, bad, tid);
+        if (ks == 3 * S::KSTEPS / 4) S::template unpack_phase<3>(ld, y, nst, sy, sw, bad, tid);
       }
       if constexpr (M2) {
-        if (ks == S::LOAD_PHASE) S::template load<ALIGNED>(p, m, f, t0, t1, c + 2, stride, tid, ld);
+        if (ks == S::LOAD_PHASE * S::KSTEPS / 4)
+          S::template load<ALIGNED>(p, m, f, t0, t1, c + 2, stride, tid, ld);
       }
     }
     if constexpr (M1) S::publish_bad(bad, s_bad, (c + 1) & 1, tid);
@@ -596,6 +599,188 @@ __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1
   __syncthreads();
 }
 
+// ---- fp8 (E4M3) staging and diagonal unit -------------------------------------
+//
+// The fp8 engine multiplies the unbiased operands
+//     A_i = (re_i, im_i)            in [-7, 7]
+//     B_j = (re_j + im_j, im_j - re_j) in [-14, 14]
+// all exactly representable in E4M3, so G = A B^T needs no correction terms:
+// 2 Re V_ij = G[i][j] + G[j][i], 2 Im V_ij = G[j][i] - G[i][j].  Products are
+// integers of magnitude <= 98 per sample, accumulated in fp32 by
+// v_mfma_f32_32x32x64_f8f6f4; a work unit spans at most kMaxUnitTimeF8 samples
+// so every partial sum is an integer below 2^24 (exact), and the epilogue
+// folds it into the int32 accumulator by an exact conversion.
+//
+// Stage row layout (per input, TC = 64 samples): A bytes then B bytes, 128
+// each; 16-byte chunk k holds samples 8k..8k+7 as four dwords of two samples,
+// [re(t), re(t+1), im(t), im(t+1)] in A and [s(t), s(t+1), d(t), d(t+1)] in B
+// (the K order is the same in both operands, which is all the product needs).
+template <int ROWS, int NT>
+struct StageF8 {
+  using L = Stage<ROWS, 64, NT>;  // same loads and item geometry as int8
+  static constexpr int QUADS = L::QUADS;
+  static constexpr int ITER = L::ITER;
+  static constexpr int ROWB = 128;
+  static constexpr int BYTES = 2 * ROWS * ROWB;      // A then B
+  static constexpr int KSTEPS = 2;                   // K=64 (32-sample) MFMA steps per chunk
+  static constexpr int LOAD_PHASE = L::LOAD_PHASE;
+  static constexpr bool FP8 = true;
+  static_assert(ITER == 1, "one unpack item per thread");
+  using Map = typename L::Map;
+
+  template <bool ALIGNED>
+  __device__ static void load(const Problem& p, const Map& m, int f, int t0, int t1, int c, int64_t stride, int tid,
+                              uint32_t (&ld)[ITER][8]) {
+    L::template load<ALIGNED>(p, m, f, t0, t1, c, stride, tid, ld);
+  }
+
+  // Two samples (bytes 2h, 2h+1 of y) of one input -> one A dword and one B
+  // dword of E4M3 codes.  u = re + 8, w = im + 8 become f16 via 1024 + u.
+  __device__ static void to_fp8(uint32_t y, int h, uint32_t& a, uint32_t& b) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    const uint32_t sel = h ? 0x04030402u : 0x04010400u;
+    const uint32_t u = bre4(y), w = bim4(y);
+    const h2 bias = {(_Float16)1032.0f, (_Float16)1032.0f};
+    const h2 re = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, u, sel)) - bias;
+    const h2 im = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, w, sel)) - bias;
+    const h2 sm = re + im, df = im - re;
+    s2 va = {0, 0}, vb = {0, 0};
+    va = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(va, re, 1.0f, false);
+    va = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(va, im, 1.0f, true);
+    vb = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(vb, sm, 1.0f, false);
+    vb = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(vb, df, 1.0f, true);
+    a = __builtin_bit_cast(uint32_t, va);
+    b = __builtin_bit_cast(uint32_t, vb);
+  }
+
+  // Phases 0/1: transpose rows 0-3 / 4-7 and bias; phases 2/3: inputs 0-1 /
+  // 2-3 -- invalid samples zeroed (rare branch), conversion, one 16-byte store
+  // of A and one of B per input.
+  template <int PH>
+  __device__ static void unpack_phase(const uint32_t (&ld)[ITER][8], uint32_t (&y)[8], uint8_t* st,
+                                      uint32_t (&)[ITER][4], uint32_t (&)[ITER][4], uint32_t& bad, int tid) {
+    if (!L::has_item(tid, 0)) return;
+    if constexpr (PH < 2) {
+      L::transpose_tq(ld, y, 0, PH, bad);
+    } else {
+      if (PH == 2 && (bad & 0x88888888u)) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y[k] = mask_invalid(y[k]);
+      }
+      const int q = tid % QUADS, g = tid / QUADS;
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const int c = 2 * (PH - 2) + cc;
+        const int row = 4 * q + c;
+        v4i va, vb;
+        uint32_t a0, b0, a1, b1, a2, b2, a3, b3;
+        to_fp8(y[2 * c], 0, a0, b0);
+        to_fp8(y[2 * c], 1, a1, b1);
+        to_fp8(y[2 * c + 1], 0, a2, b2);
+        to_fp8(y[2 * c + 1], 1, a3, b3);
+        va = v4i{(int)a0, (int)a1, (int)a2, (int)a3};
+        vb = v4i{(int)b0, (int)b1, (int)b2, (int)b3};
+        const int off = row * ROWB + ((g ^ L::swz(row)) << 4);
+        *reinterpret_cast<v4i*>(st + off) = va;
+        *reinterpret_cast<v4i*>(st + ROWS * ROWB + off) = vb;
+      }
+    }
+  }
+
+  __device__ static void unpack_all(const uint32_t (&ld)[ITER][8], uint8_t* st, uint32_t (&sy)[ITER][4],
+                                    uint32_t (&sw)[ITER][4], uint32_t& bad, int tid) {
+    uint32_t y[8];
+    unpack_phase<0>(ld, y, st, sy, sw, bad, tid);
+    unpack_phase<1>(ld, y, st, sy, sw, bad, tid);
+    unpack_phase<2>(ld, y, st, sy, sw, bad, tid);
+    unpack_phase<3>(ld, y, st, sy, sw, bad, tid);
+  }
+
+  // Invalid samples are zeroed during the unpack: nothing to publish or fix.
+  __device__ static void publish_bad(uint32_t, uint32_t*, int, int) {}
+  __device__ static void check_bad(uint8_t*, uint32_t*, int, uint32_t*, uint32_t*, int) {}
+
+  // 32 bytes (16 samples) of one input for a K=64 step; `part` = 2 ks + half.
+  __device__ static v8i read_frag(const uint8_t* arr, int row, int part) {
+    const uint8_t* base = arr + row * ROWB;
+    const v4i lo = *reinterpret_cast<const v4i*>(base + (((2 * part) ^ L::swz(row)) << 4));
+    const v4i hi = *reinterpret_cast<const v4i*>(base + (((2 * part + 1) ^ L::swz(row)) << 4));
+    return v8i{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  }
+};
+
+// One fp8 diagonal unit of 256 inputs (inputs ibase ..), 8 waves.
+template <bool ALIGNED>
+__device__ void run_diag_f8(const Problem& p, int f, int ibase, int t0, int t1, int tid, uint8_t* lds,
+                            uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  using G = DiagGeom<256, 4>;
+  using S = StageF8<256, G::NT>;
+  static_assert(2 * S::BYTES <= G::LDS, "two fp8 stage buffers fit in the unit's LDS");
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / 4, wc = wave % 4;
+  const int nchunks = t1 > t0 ? (t1 - t0 + 63) / 64 : 0;
+  const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
+
+  for (int k = tid; k < 256; k += G::NT) {
+    s_sy[k] = 0;  // no correction terms in the unbiased formulation
+    s_sw[k] = 0;
+  }
+  if (tid < 2) s_bad[tid] = 0;
+  __syncthreads();
+
+  v16f acc[G::FM][G::FN];
+#pragma unroll
+  for (int x = 0; x < G::FM; ++x)
+#pragma unroll
+    for (int z = 0; z < G::FN; ++z) acc[x][z] = v16f{0.0f};
+  uint32_t sy[1][4], sw[1][4];
+
+  const int half = lane >> 5;
+  const int rrow = wr * G::TM + (lane & 31), crow = wc * G::TN + (lane & 31);
+  const typename S::Map m{ibase, 64, ibase};
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, s_bad, sy, sw, nchunks,
+                         [&](const uint8_t* st, int ks) {
+                           v8i a[G::FM], b[G::FN];
+#pragma unroll
+                           for (int x = 0; x < G::FM; ++x) a[x] = S::read_frag(st, rrow + 32 * x, 2 * ks + half);
+#pragma unroll
+                           for (int x = 0; x < G::FN; ++x)
+                             b[x] = S::read_frag(st + 256 * S::ROWB, crow + 32 * x, 2 * ks + half);
+#pragma unroll
+                           for (int x = 0; x < G::FM; ++x)
+#pragma unroll
+                             for (int z = 0; z < G::FN; ++z)
+                               acc[x][z] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[x], b[z], acc[x][z], 0,
+                                                                                           0, 0, 0, 0, 0);
+                         });
+
+  // Exact fold: every accumulator holds an integer below 2^24.
+  v16i iacc[G::FM][G::FN];
+#pragma unroll
+  for (int x = 0; x < G::FM; ++x)
+#pragma unroll
+    for (int z = 0; z < G::FN; ++z)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) iacc[x][z][r] = (int)acc[x][z][r];
+
+  __syncthreads();
+  int* xa = reinterpret_cast<int*>(lds);
+  int* xb = xa + G::XAREA;
+  constexpr int HW = 2;
+  if (wr == 0 && wc >= HW) store_tile<G>(xa, (wc - HW) * G::TN, iacc, lane);
+  if (wr == 1 && wc < HW) store_tile<G>(xb, wc * G::TN, iacc, lane);
+  __syncthreads();
+  combine_quadrant<G>(p, f, ibase, xb, xa, G::H, 0, s_sy, s_sw, 0u, mode, tid);
+  __syncthreads();
+  if (wr == 0 && wc < HW) store_tile<G>(xa, wc * G::TN, iacc, lane);
+  if (wr == 1 && wc >= HW) store_tile<G>(xb, (wc - HW) * G::TN, iacc, lane);
+  __syncthreads();
+  combine_quadrant<G>(p, f, ibase, xa, xa, 0, 0, s_sy, s_sw, 0u, mode, tid);
+  combine_quadrant<G>(p, f, ibase, xb, xb, G::H, G::H, s_sy, s_sw, 0u, mode, tid);
+  __syncthreads();
+}
+
 // ---- standalone grids -----------------------------------------------------------
 
 // Map the hardware workgroup id so that consecutive logical units land on the
@@ -651,6 +836,17 @@ __global__ __launch_bounds__(512, 1) void xmac_pair_i8(Problem p, int npair, int
   run_pair<ALIGNED>(p, f, I0, J0, t0, t1, threadIdx.x, lds, s_sy, s_sw, s_bad, nsplit > 1 ? (int)kWriteAtomic : mode);
 }
 
+template <bool ALIGNED>
+__global__ __launch_bounds__(512, 1) void xmac_diag_f8(Problem p, int nsplit, int tsplit, int mode) {
+  using G = DiagGeom<256, 4>;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[G::LDS];
+  __shared__ uint32_t s_sy[256], s_sw[256], s_bad[2];
+  int u = xcd_remap(blockIdx.x, gridDim.x);
+  const int sp = u % nsplit, f = u / nsplit;
+  const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
+  run_diag_f8<ALIGNED>(p, f, 0, t0, t1, threadIdx.x, lds, s_sy, s_sw, s_bad, nsplit > 1 ? (int)kWriteAtomic : mode);
+}
+
 static bool aligned_problem(const Problem& p) {
   const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
   return (p.n_inputs % 4 == 0) && ((reinterpret_cast<uintptr_t>(p.in) & 3) == 0) &&
@@ -691,9 +887,23 @@ int mfma_units_per_channel(int n_inputs) {
   return nb + nb * (nb - 1);
 }
 
+static int launch_f8(const Problem& p, int nsplit, int mode, hipStream_t s) {
+  if (p.n_inputs > 256) return CORRX_EUNSUPPORTED;
+  const int tsplit = (p.n_time + nsplit - 1) / nsplit;
+  if (tsplit > kMaxUnitTimeF8) return CORRX_EINVAL;
+  const int64_t grid = (int64_t)p.n_chan * nsplit;
+  if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
+  if (aligned_problem(p))
+    hipLaunchKernelGGL((xmac_diag_f8<true>), dim3((unsigned)grid), dim3(512), 0, s, p, nsplit, tsplit, mode);
+  else
+    hipLaunchKernelGGL((xmac_diag_f8<false>), dim3((unsigned)grid), dim3(512), 0, s, p, nsplit, tsplit, mode);
+  return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
+}
+
 int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, hipStream_t s) {
-  if (engine != CORRX_ENGINE_MFMA_I8) return CORRX_EUNSUPPORTED;
   (void)tile_cfg;
+  if (engine == CORRX_ENGINE_MFMA_F8) return launch_f8(p, nsplit, mode, s);
+  if (engine != CORRX_ENGINE_MFMA_I8) return CORRX_EUNSUPPORTED;
   if (p.n_inputs <= 64) return launch_diag<64, 2>(p, 1, nsplit, mode, s);
   if (p.n_inputs <= 128) return launch_diag<128, 2>(p, 1, nsplit, mode, s);
   const int nb = (p.n_inputs + 255) / 256;

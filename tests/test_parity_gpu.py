@@ -8,7 +8,8 @@ from paper_1501_05992_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-ENGINES = ["plain", "mfma_i8"]
+ENGINES = ["plain", "mfma_i8", "mfma_f8"]
+ENGINES_ANY_N = ["plain", "mfma_i8"]  # the fp8 engine serves up to 256 inputs
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +66,7 @@ def test_input_counts(cx, oracle_lib, engine, n):
     _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} N={n}")
 
 
-@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("engine", ENGINES_ANY_N)
 @pytest.mark.parametrize("n", [257, 300, 384, 511, 512, 513, 700, 1024])
 def test_multi_block_input_counts(cx, oracle_lib, engine, n):
     # more than 256 inputs: diagonal blocks plus pair units
@@ -256,3 +257,26 @@ def test_batch_rejects_unaligned_inputs(cx):
     assert e.value.status == cx.CORRX_EUNSUPPORTED
     with pytest.raises(cx.CorrxError):
         cx.Batch([(256, 2, 10, 0)], tile_cfg=[cx.CORRX_TILE_UNIT64])
+
+
+@pytest.mark.parametrize("tc", [131072, 131073, 171197])
+def test_fp8_exact_at_the_fp32_bound(cx, oracle_lib, tc):
+    # every sample 7+7j: |G| grows by 98 per sample, the largest possible, so
+    # fp32 partial sums reach 98 * 2^17 within one work unit
+    n, fc = 32, 1
+    buf = np.full(n * fc * tc, 0x77, dtype=np.uint8)
+    got = _run(cx, buf, n, fc, tc, engine="mfma_f8")
+    want = oracle_lib.xmac(buf[: n * 1000], n, fc, 1000) * tc // 1000
+    _compare(got, want, n, f"fp8 T={tc}")
+
+
+def test_fp8_rejects_large_arrays(cx):
+    c = cx.Correlator(300, 1, 10, engine="mfma_f8")
+    import torch
+
+    x = torch.zeros(3000, dtype=torch.uint8, device="cuda")
+    acc = c.new_acc()
+    with pytest.raises(cx.CorrxError) as e:
+        c.xmac(x, acc)
+    assert e.value.status == cx.CORRX_EUNSUPPORTED
+    c.close()
