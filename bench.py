@@ -188,17 +188,26 @@ def time_xmac(corrx, torch, c, x, acc, reps):
 
 
 def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
+    import oracle
+
     out = {}
-    # plain (vector ALU) engine on the same full-band input
-    c = corrx.Correlator(n, fc, tc, corrx.CORRX_LAYOUT_TFI, "plain")
-    acc = c.new_acc(dev)
-    ms = time_xmac(corrx, torch, c, x, acc, 3)
     ops = model.alg_ops(n, fc, tc)
-    out["full_band_plain"] = {"xmac_ms": round(ms, 3), "tops": round(ops / ms / 1e9, 2),
-                              "xrt": round(model.realtime_factor(tc, ms * 1e-3), 1)}
-    c.close()
-    del acc
-    # one coarse channel: 256 inputs x 128 channels x 5000 samples, both engines
+    # the full band on the other two engines
+    for eng, reps in (("mfma_f8", 10), ("plain", 3)):
+        c = corrx.Correlator(n, fc, tc, corrx.CORRX_LAYOUT_TFI, eng)
+        acc = c.new_acc(dev)
+        ms = time_xmac(corrx, torch, c, x, acc, reps)
+        ok = bool(np.array_equal(acc[0].cpu().numpy().astype(np.int64),
+                                 oracle.xmac(np.ascontiguousarray(synth.channel_view(host, 0, n, fc, tc, 0)),
+                                             n, 1, tc)[0]))
+        out[f"full_band_{eng}"] = {"xmac_ms": round(ms, 3), "tops": round(ops / ms / 1e9, 2),
+                                   "frac_of_peak": round(ops / ms / 1e9 / PEAK_INT8_TOPS, 4),
+                                   "xrt": round(model.realtime_factor(tc, ms * 1e-3), 1),
+                                   "channel0_bit_exact": ok}
+        c.close()
+        del acc
+        log(f"full band {eng}: {ms:.3f} ms")
+    # one coarse channel: 256 inputs x 128 channels x 5000 samples, int8 MFMA vs plain
     n2, f2, t2 = 256, 128, 5000
     h2 = synth.make_input(synth.config_seed(1), n2, f2, t2)
     x2 = torch.from_numpy(h2).to(dev)
@@ -206,11 +215,67 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
         c = corrx.Correlator(n2, f2, t2, corrx.CORRX_LAYOUT_TFI, eng)
         acc = c.new_acc(dev)
         ms = time_xmac(corrx, torch, c, x2, acc, 20)
-        ops = model.alg_ops(n2, f2, t2)
-        out[f"coarse_channel_{eng}"] = {"xmac_ms": round(ms, 4), "tops": round(ops / ms / 1e9, 2),
+        ops2 = model.alg_ops(n2, f2, t2)
+        out[f"coarse_channel_{eng}"] = {"xmac_ms": round(ms, 4), "tops": round(ops2 / ms / 1e9, 2),
                                         "xrt": round(model.realtime_factor(t2, ms * 1e-3), 1)}
         c.close()
+    del x2
+    out["uneven_batch"] = uneven_batch(corrx, model, synth, torch, dev, oracle)
     return out
+
+
+UNEVEN = [(64, 3072, 10000, 0), (256, 768, 5000, 0), (512, 384, 4000, 0), (2048, 128, 2000, 0)]
+
+
+def uneven_batch(corrx, model, synth, torch, dev, oracle):
+    """Arrays of 64/256/512/2048 inputs in one persistent launch, tile codes
+    from the autotuner; each array also timed alone through corr_xmac."""
+    from paper_1501_05992_amd import tune
+
+    seed = synth.config_seed(3)
+    hosts = [synth.make_input(seed, n, f, t, array=k) for k, (n, f, t, lay) in enumerate(UNEVEN)]
+    ins = [torch.from_numpy(h).to(dev) for h in hosts]
+    probe = corrx.Batch(UNEVEN)
+    accs = probe.new_accs(dev)
+    probe.close()
+    log("autotuning the uneven batch")
+    codes, report = tune.tune_batch(UNEVEN, ins, accs, use_cache=False)
+    b = corrx.Batch(UNEVEN, tile_cfg=codes)
+    plan = [b.plan(k) for k in range(len(UNEVEN))]
+    b.zero(accs)
+    b.xmac(ins, accs)
+    torch.cuda.synchronize()
+    checks = []
+    for (n, f, t, lay), h, acc in zip(UNEVEN, hosts, accs):
+        ch = np.ascontiguousarray(synth.channel_view(h, lay, n, f, t, f - 1))
+        checks.append(bool(np.array_equal(acc[f - 1].cpu().numpy().astype(np.int64), oracle.xmac(ch, n, 1, t)[0])))
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for e0, e1 in evs:
+        b.zero(accs)
+        e0.record(s)
+        b.xmac(ins, accs)
+        e1.record(s)
+    torch.cuda.synchronize()
+    ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+    ops = sum(model.alg_ops(n, f, t) for (n, f, t, lay) in UNEVEN)
+    alone = []
+    for (n, f, t, lay), xin in zip(UNEVEN, ins):
+        c = corrx.Correlator(n, f, t, lay)
+        acc = c.new_acc(dev)
+        ams = time_xmac(corrx, torch, c, xin, acc, 5)
+        alone.append({"n_inputs": n, "n_chan": f, "n_time": t, "xmac_ms": round(ams, 3),
+                      "tops": round(model.alg_ops(n, f, t) / ams / 1e9, 1)})
+        c.close()
+        del acc
+    res = {"arrays": [list(d[:3]) for d in UNEVEN], "tile_codes": [hex(c) for c in codes],
+           "plan_kind_splits": plan, "items": b.items, "ms": round(ms, 3), "tops": round(ops / ms / 1e9, 1),
+           "frac_of_peak": round(ops / ms / 1e9 / PEAK_INT8_TOPS, 4), "alone": alone,
+           "alone_sum_ms": round(sum(a["xmac_ms"] for a in alone), 3),
+           "sampled_channel_bit_exact": checks}
+    b.close()
+    log(f"uneven batch: {ms:.3f} ms ({res['tops']} TOPS), alone sum {res['alone_sum_ms']} ms")
+    return res
 
 
 def cpu_baseline(oracle, model, synth, host, n, fc, tc, n_ch):

@@ -193,6 +193,14 @@ int64_t corr_batch_items(corrx_batch_t b);
 int corr_batch_plan(corrx_batch_t b, int array, int *kind, int *splits);
 
 /*
+ * Set every accumulator of the batch to zero (one fill launch per array).  The
+ * next corr_batch_xmac with the same accumulators then writes instead of
+ * adding, as corr_xmac does after corr_zero; the caller must not modify them
+ * in between.  accs: HOST array of n DEVICE pointers.
+ */
+int corr_batch_zero(corrx_batch_t b, void *const *accs, void *stream);
+
+/*
  * For every array a: accs[a] += V(ins[a]).  ins and accs are HOST arrays of n
  * DEVICE pointers (same meaning as for corr_xmac, one per array; accs 8-byte
  * aligned).  One persistent launch (plus a one-thread queue reset) on `stream`.

@@ -46,7 +46,7 @@ ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
 SYMBOLS = ("corr_abi_version", "corr_strerror", "corr_create", "corr_destroy", "corr_set_engine",
            "corr_get_engine", "corr_acc_bytes", "corr_dump_count", "corr_zero", "corr_xmac",
            "corr_dump", "corr_samples", "corr_beam", "corr_batch_create", "corr_batch_destroy",
-           "corr_batch_items", "corr_batch_plan", "corr_batch_xmac")
+           "corr_batch_items", "corr_batch_plan", "corr_batch_zero", "corr_batch_xmac")
 
 
 class CorrxError(RuntimeError):
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
             "corr_batch_destroy": ([vp], i),
             "corr_batch_items": ([vp], i64),
             "corr_batch_plan": ([vp, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+            "corr_batch_zero": ([vp, ctypes.POINTER(vp), vp], i),
             "corr_batch_xmac": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp], i),
         }
         for name, (args, res) in sig.items():
@@ -202,6 +203,12 @@ def corr_batch_plan(b: int, array: int) -> tuple[int, int]:
     return kind.value, splits.value
 
 
+def corr_batch_zero(b: int, accs, stream=None) -> None:
+    n = len(accs)
+    pacc = (ctypes.c_void_p * n)(*[_ptr(x) for x in accs])
+    _check(lib().corr_batch_zero(b, pacc, _stream(stream)), "corr_batch_zero")
+
+
 def corr_batch_xmac(b: int, ins, accs, stream=None) -> None:
     n = len(ins)
     pin = (ctypes.c_void_p * n)(*[_ptr(x) for x in ins])
@@ -297,6 +304,9 @@ class Batch:
     def new_accs(self, device="cuda"):
         return [torch.zeros((f, n * (n + 1) // 2, 2), dtype=torch.int32, device=device)
                 for (n, f, t, lay) in self.descs]
+
+    def zero(self, accs, stream=None) -> None:
+        corr_batch_zero(self.h, accs, stream)
 
     def xmac(self, ins, accs, stream=None) -> None:
         corr_batch_xmac(self.h, ins, accs, stream)

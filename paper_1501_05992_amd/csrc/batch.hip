@@ -21,6 +21,7 @@ struct corrx_batch {
   int n_items;
   WorkItem* d_items;
   int* d_counter;
+  void* zeroed[kMaxBatch];  // accumulators set to zero by corr_batch_zero and not written since
 };
 
 namespace {
@@ -168,13 +169,13 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
   b->n_items = (int)items.size();
   if (hipMalloc(&b->d_items, sizeof(WorkItem) * items.size()) != hipSuccess ||
       hipMalloc(&b->d_counter, sizeof(int)) != hipSuccess) {
-    hipFree(b->d_items);
+    (void)hipFree(b->d_items);
     delete b;
     return CORRX_ENOMEM;
   }
   if (hipMemcpy(b->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(b->d_items);
-    hipFree(b->d_counter);
+    (void)hipFree(b->d_items);
+    (void)hipFree(b->d_counter);
     delete b;
     return CORRX_EDEVICE;
   }
@@ -184,8 +185,8 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
 
 int corr_batch_destroy(corrx_batch_t b) {
   if (!b) return CORRX_OK;
-  hipFree(b->d_items);
-  hipFree(b->d_counter);
+  (void)hipFree(b->d_items);
+  (void)hipFree(b->d_counter);
   delete b;
   return CORRX_OK;
 }
@@ -199,10 +200,24 @@ int corr_batch_plan(corrx_batch_t b, int array, int* kind, int* splits) {
   return CORRX_OK;
 }
 
+int corr_batch_zero(corrx_batch_t b, void* const* accs, void* stream) {
+  if (!b || !accs) return CORRX_EINVAL;
+  for (int a = 0; a < b->n; ++a)
+    if (!accs[a]) return CORRX_EINVAL;
+  for (int a = 0; a < b->n; ++a) {
+    const int64_t words = (int64_t)b->d[a].n_chan * tri_index(b->d[a].n_inputs, 0) * 2;
+    const int rc = launch_zero(static_cast<int*>(accs[a]), words, reinterpret_cast<hipStream_t>(stream));
+    if (rc != CORRX_OK) return rc;
+    b->zeroed[a] = accs[a];
+  }
+  return CORRX_OK;
+}
+
 int corr_batch_xmac(corrx_batch_t b, const void* const* ins, void* const* accs, void* stream) {
   if (!b || !ins || !accs) return CORRX_EINVAL;
   BatchArgs args;
   memset(&args, 0, sizeof(args));
+  int fresh = 1;
   for (int a = 0; a < b->n; ++a) {
     if (!ins[a] || !accs[a]) return CORRX_EINVAL;
     if ((reinterpret_cast<uintptr_t>(ins[a]) & 3) || (reinterpret_cast<uintptr_t>(accs[a]) & 7)) return CORRX_EINVAL;
@@ -213,10 +228,15 @@ int corr_batch_xmac(corrx_batch_t b, const void* const* ins, void* const* accs, 
     p.n_chan = b->d[a].n_chan;
     p.n_time = b->d[a].n_time;
     p.layout = b->d[a].layout;
+    fresh &= b->zeroed[a] == accs[a];
   }
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return CORRX_EDEVICE;
-  return launch_batch(args, b->d_items, b->n_items, b->d_counter, b->grid, reinterpret_cast<hipStream_t>(stream));
+  // Freshly zeroed accumulators (all of them) are overwritten, not added to.
+  const int rc = launch_batch(args, b->d_items, b->n_items, b->d_counter, b->grid, fresh ? kWriteStore : kWriteAdd,
+                              reinterpret_cast<hipStream_t>(stream));
+  for (int a = 0; a < b->n; ++a) b->zeroed[a] = nullptr;
+  return rc;
 }
 
 }  // extern "C"

@@ -155,7 +155,9 @@ struct BatchArgs {
   Problem arrays[kMaxBatch];
 };
 
+// base_mode: kWriteStore (all accumulators freshly zeroed) or kWriteAdd; items
+// with time splits always add atomically.
 int launch_batch(const BatchArgs& args, const WorkItem* d_items, int n_items, int* d_counter, int grid,
-                 hipStream_t s);
+                 int base_mode, hipStream_t s);
 
 }  // namespace corrx

@@ -445,6 +445,10 @@ __device__ inline void combine_quadrant(const Problem& p, int f, int ibase, cons
 template <int NB, int WC, bool ALIGNED>
 __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int tid, uint8_t* lds, uint32_t* s_sy,
                          uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  // Values derived from the thread index are recomputed for every unit: when
+  // units run in a loop (the persistent kernel), hoisting them out of it would
+  // keep them live across the whole unit and exhaust the registers.
+  asm volatile("" : "+v"(tid));
   using G = DiagGeom<NB, WC>;
   using S = Stage<NB, 64, G::NT>;
   const int lane = tid & 63, wave = tid >> 6;
@@ -521,6 +525,10 @@ struct PairGeom {
 template <bool ALIGNED>
 __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1, int tid, uint8_t* lds,
                          uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  // Values derived from the thread index are recomputed for every unit: when
+  // units run in a loop (the persistent kernel), hoisting them out of it would
+  // keep them live across the whole unit and exhaust the registers.
+  asm volatile("" : "+v"(tid));
   using S = Stage<PairGeom::ROWS, 64, PairGeom::NT>;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave / 4, wc = wave % 4;
@@ -714,6 +722,10 @@ struct StageF8 {
 template <bool ALIGNED>
 __device__ void run_diag_f8(const Problem& p, int f, int ibase, int t0, int t1, int tid, uint8_t* lds,
                             uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+  // Values derived from the thread index are recomputed for every unit: when
+  // units run in a loop (the persistent kernel), hoisting them out of it would
+  // keep them live across the whole unit and exhaust the registers.
+  asm volatile("" : "+v"(tid));
   using G = DiagGeom<256, 4>;
   using S = StageF8<256, G::NT>;
   static_assert(2 * S::BYTES <= G::LDS, "two fp8 stage buffers fit in the unit's LDS");
@@ -918,76 +930,94 @@ constexpr int kBatchLds =
     DiagGeom<256, 4>::LDS > PairGeom::LDS ? DiagGeom<256, 4>::LDS : PairGeom::LDS;
 static_assert(2 * DiagGeom<128, 2>::LDS <= kBatchLds, "two 128-input units fit side by side");
 
-// Each unit kind of the batch kernel in its own function, so that each gets
-// its own register allocation.
-__device__ __noinline__ void batch_diag256(const Problem& p, int f, int blk, int t0, int t1, int tid, uint8_t* lds,
-                                           uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
-  run_diag<256, 4, true>(p, f, blk * 256, t0, t1, tid, lds, s_sy, s_sw, s_bad, mode);
+// Next work item of the persistent kernel (same value in every thread).
+__device__ inline int batch_fetch(int* counter, int* s_item) {
+  if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
+  __syncthreads();
+  const int it = *s_item;
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(it);
 }
-__device__ __noinline__ void batch_pair(const Problem& p, int f, int pu, int t0, int t1, int tid, uint8_t* lds,
-                                        uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
-  int I0, J0;
-  pair_decode(pu, I0, J0);
-  run_pair<true>(p, f, I0, J0, t0, t1, tid, lds, s_sy, s_sw, s_bad, mode);
+
+__device__ inline WorkItem batch_item(const WorkItem* items, int it) {
+  WorkItem w;
+  w.array = __builtin_amdgcn_readfirstlane(items[it].array);
+  w.channel = __builtin_amdgcn_readfirstlane(items[it].channel);
+  w.tile = __builtin_amdgcn_readfirstlane(items[it].tile);
+  w.t0 = __builtin_amdgcn_readfirstlane(items[it].t0);
+  w.t1 = __builtin_amdgcn_readfirstlane(items[it].t1);
+  w.kind = __builtin_amdgcn_readfirstlane(items[it].kind);
+  w.atomic = __builtin_amdgcn_readfirstlane(items[it].atomic);
+  return w;
 }
+
+// Items of the two-channel kinds (64 or 128 inputs).  Kept out of line, with
+// its own register allocation, and it keeps pulling items while they are of
+// its kind, so the call happens once per run of such items.  Returns the
+// first item it fetched that is of another kind (or past the end).
 template <int NB>
-__device__ __noinline__ void batch_small_x2(const Problem& p, int f0, int t0, int t1, int tid, uint8_t* lds,
-                                            uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
-  const int g = tid >> 8, f = f0 + g;
-  run_diag<NB, 2, true>(p, min(f, p.n_chan - 1), 0, t0, t1, tid & 255, lds + g * DiagGeom<NB, 2>::LDS, s_sy + NB * g,
-                        s_sw + NB * g, s_bad, f < p.n_chan ? mode : (int)kWriteNone);
+__device__ __noinline__ int batch_small_run(const Problem* table, const WorkItem* items, int n_items, int* counter,
+                                            int it, int base_mode, uint8_t* lds, uint32_t* s_sy, uint32_t* s_sw,
+                                            uint32_t* s_bad, int* s_item) {
+  constexpr int kind = NB == 64 ? kUnitDiag64x2 : kUnitDiag128x2;
+  while (it < n_items) {
+    const WorkItem w = batch_item(items, it);
+    if (w.kind != kind) break;
+    const Problem p = table[w.array];
+    const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
+    const int tid = threadIdx.x;
+    const int g = tid >> 8, f = w.channel + g;
+    run_diag<NB, 2, true>(p, min(f, p.n_chan - 1), 0, w.t0, w.t1, tid & 255, lds + g * DiagGeom<NB, 2>::LDS,
+                          s_sy + NB * g, s_sw + NB * g, s_bad, f < p.n_chan ? mode : (int)kWriteNone);
+    it = batch_fetch(counter, s_item);
+  }
+  return it;
 }
 
 // One workgroup per compute unit pulls work items from a device counter until
 // the list is exhausted.  Every item is one unit (or two small units side by
 // side, on channels f and f+1 of the same array).  All arrays must be aligned.
 __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const WorkItem* items, int n_items,
-                                                         int* counter) {
+                                                         int* counter, int base_mode) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kBatchLds];
   __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS], s_bad[2];
   __shared__ int s_item;
   const int tid = threadIdx.x;
-  for (;;) {
-    if (tid == 0) s_item = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = s_item;
-    __syncthreads();
-    if (it >= n_items) break;
-    // The item is the same for every lane: keep it in scalar registers.
-    const int iu = __builtin_amdgcn_readfirstlane(it);
-    WorkItem w;
-    w.array = __builtin_amdgcn_readfirstlane(items[iu].array);
-    w.channel = __builtin_amdgcn_readfirstlane(items[iu].channel);
-    w.tile = __builtin_amdgcn_readfirstlane(items[iu].tile);
-    w.t0 = __builtin_amdgcn_readfirstlane(items[iu].t0);
-    w.t1 = __builtin_amdgcn_readfirstlane(items[iu].t1);
-    w.kind = __builtin_amdgcn_readfirstlane(items[iu].kind);
-    w.atomic = __builtin_amdgcn_readfirstlane(items[iu].atomic);
-    const Problem p = args.arrays[w.array];
-    const int mode = w.atomic ? (int)kWriteAtomic : (int)kWriteAdd;
-    switch (w.kind) {
-      case kUnitDiag256:
-        batch_diag256(p, w.channel, w.tile, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
-        break;
-      case kUnitPair:
-        batch_pair(p, w.channel, w.tile, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
-        break;
-      case kUnitDiag128x2:
-        batch_small_x2<128>(p, w.channel, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
-        break;
-      default:  // kUnitDiag64x2
-        batch_small_x2<64>(p, w.channel, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
-        break;
+  // The problem table is the first kernel argument: read it in place in the
+  // kernel-argument segment (taking the address of the by-value parameter
+  // would copy it to private memory).
+  (void)args;
+  const Problem* table = (const Problem*)__builtin_amdgcn_kernarg_segment_ptr();
+  int it = batch_fetch(counter, &s_item);
+  while (it < n_items) {
+    const WorkItem w = batch_item(items, it);
+    if (w.kind == kUnitDiag64x2) {
+      it = batch_small_run<64>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, s_bad, &s_item);
+      continue;
     }
+    if (w.kind == kUnitDiag128x2) {
+      it = batch_small_run<128>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, s_bad, &s_item);
+      continue;
+    }
+    const Problem p = table[w.array];
+    const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
+    if (w.kind == kUnitDiag256) {
+      run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
+    } else {
+      int I0, J0;
+      pair_decode(w.tile, I0, J0);
+      run_pair<true>(p, w.channel, I0, J0, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
+    }
+    it = batch_fetch(counter, &s_item);
   }
 }
 
 __global__ void reset_counter(int* counter) { *counter = 0; }
 
 int launch_batch(const BatchArgs& args, const WorkItem* d_items, int n_items, int* d_counter, int grid,
-                 hipStream_t s) {
+                 int base_mode, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, d_counter);
-  hipLaunchKernelGGL(xmac_batch_i8, dim3(grid), dim3(512), 0, s, args, d_items, n_items, d_counter);
+  hipLaunchKernelGGL(xmac_batch_i8, dim3(grid), dim3(512), 0, s, args, d_items, n_items, d_counter, base_mode);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 

@@ -222,8 +222,9 @@ def test_batch_uneven_arrays(cx, oracle_lib, tile_cfg):
     b = cx.Batch(descs, tile_cfg=cfg)
     assert b.items > 0
     ins = [torch.from_numpy(x).cuda() for x in bufs]
-    accs = b.new_accs()
-    b.xmac(ins, accs)
+    accs = [a.fill_(7) for a in b.new_accs()]
+    b.zero(accs)
+    b.xmac(ins, accs)  # writes
     b.xmac(ins, accs)  # accumulates
     torch.cuda.synchronize()
     for (n, f, t, lay), x, acc in zip(descs, bufs, accs):
