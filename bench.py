@@ -221,7 +221,60 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
         c.close()
     del x2
     out["uneven_batch"] = uneven_batch(corrx, model, synth, torch, dev, oracle)
+    out["streaming"] = streaming(synth, torch)
     return out
+
+
+STREAM = [("obs256x3072", 256, 3072), ("obs256x768", 256, 768), ("obs512x384", 512, 384), ("obs128x3072", 128, 3072)]
+
+
+def streaming(synth, torch, paced_integrations=26, flat_integrations=6):
+    """Four observations fed in 50 ms chunks (500 samples), 0.5 s integrations,
+    accumulators on the device, admission by a device-memory budget that holds
+    only some of them at once.  Paced: chunks released in real time, latency
+    per integration.  Flat out: chunks as fast as the device takes them."""
+    from paper_1501_05992_amd.service import CHUNK_SAMPLES, GpuBackend, Observation, Service
+
+    pools = {}
+    for k, (name, n, f) in enumerate(STREAM):
+        host = synth.make_input(synth.config_seed(4), n, f, 2 * CHUNK_SAMPLES, array=k)
+        pools[name] = (torch.from_numpy(host).pin_memory(), n * f * CHUNK_SAMPLES)
+
+    def make(n_int, arrivals):
+        obs = []
+        for (name, n, f), arr in zip(STREAM, arrivals):
+            pin, per = pools[name]
+            obs.append(Observation(name, n, f, n_int, lambda k, d=pin, p=per: d[(k % 2) * p:(k % 2 + 1) * p],
+                                   arrival_s=arr))
+        return obs
+
+    be = GpuBackend()
+    need = {o.obs_id: be.mem_bytes(o) for o in make(1, [0, 0, 0, 0])}
+    budget = need["obs256x3072"] + need["obs512x384"] + need["obs256x768"]  # the fourth has to wait
+    log(f"streaming: paced, {paced_integrations} integrations per observation, budget {budget / 1e9:.2f} GB")
+    svc = Service(be, budget)
+    for o in make(paced_integrations, [0.0, 0.25, 0.5, 0.75]):
+        svc.submit(o)
+    paced = svc.run(paced=True)
+    log(f"streaming paced: p50 {paced['latency_p50_ms']:.2f} ms, p99 {paced['latency_p99_ms']:.2f} ms")
+    svc = Service(be, sum(need.values()))
+    for o in make(flat_integrations, [0, 0, 0, 0]):
+        svc.submit(o)
+    flat = svc.run(paced=False)
+    log(f"streaming flat out: {flat['realtime_factor']:.2f}x real time")
+    rate = sum(model_bytes(n, f) for _, n, f in STREAM)
+    return {"observations": [list(x) for x in STREAM], "chunk_samples": CHUNK_SAMPLES,
+            "integration_samples": 10 * CHUNK_SAMPLES, "hbm_budget_bytes": budget,
+            "input_gb_per_data_s": round(rate / 1e9, 2),
+            "paced": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in paced.items()},
+            "flat_out": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in flat.items()
+                         if k != "admissions"}}
+
+
+def model_bytes(n, f):
+    from paper_1501_05992_amd import model
+
+    return model.input_bytes(n, f, model.SAMPLE_RATE_HZ)
 
 
 UNEVEN = [(64, 3072, 10000, 0), (256, 768, 5000, 0), (512, 384, 4000, 0), (2048, 128, 2000, 0)]
