@@ -94,7 +94,10 @@ struct Stage {
       // (scalar arithmetic) and whose range ends at the channel's last valid
       // row, so the per-lane offset is the same for all 8 rows of the item.
       const int rows = min(t1 - tb, TC);
-      const int64_t nrec0 = (int64_t)(rows - 1) * stride + p.n_inputs;
+      // 64 rows of a channel span less than 2^31 bytes (checked on the host),
+      // so the range arithmetic stays in 32-bit scalar registers.
+      const int stride32 = (int)stride;
+      const int nrec0 = (rows - 1) * stride32 + p.n_inputs;
       const uint8_t* base = p.in + row_offset(p, f, tb);
       uint32_t off[ITER];
 #pragma unroll
@@ -106,9 +109,9 @@ struct Stage {
       }
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const int64_t nr = nrec0 - (int64_t)r * stride;
+        const int nr = max(nrec0 - r * stride32, 0);
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<uint8_t*>(base + (int64_t)r * stride), (short)0, (int)(nr > 0 ? nr : 0), kBufferRsrcWord3);
+            const_cast<uint8_t*>(base + (int64_t)r * stride), (short)0, nr, kBufferRsrcWord3);
 #pragma unroll
         for (int k = 0; k < ITER; ++k) ld[k][r] = __builtin_amdgcn_raw_buffer_load_b32(rs, off[k], 0, 0);
       }
