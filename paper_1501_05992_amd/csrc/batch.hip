@@ -84,7 +84,7 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
     if (d.layout != CORRX_LAYOUT_TFI && d.layout != CORRX_LAYOUT_FTI) return CORRX_EINVAL;
     if ((double)d.n_inputs * d.n_chan * d.n_time >= 1099511627776.0) return CORRX_EINVAL;
     const int64_t stride = d.layout == CORRX_LAYOUT_TFI ? (int64_t)d.n_chan * d.n_inputs : d.n_inputs;
-    if (d.n_inputs % 4 != 0 || 64 * stride + d.n_inputs >= 0x7FFFFFFF) return CORRX_EUNSUPPORTED;
+    if (d.n_inputs % 4 != 0 || 128 * stride + d.n_inputs >= 0x7FFFFFFF) return CORRX_EUNSUPPORTED;
     if (tile_cfg) {
       const int unit = tile_cfg[a] & 0xFF, spl = (tile_cfg[a] >> 8) & 0xFFFF;
       if (unit > CORRX_TILE_UNIT256 || spl > 4096) return CORRX_EINVAL;

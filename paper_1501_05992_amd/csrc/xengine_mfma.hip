@@ -62,10 +62,15 @@ struct Stage {
   static constexpr int ITEMS = QUADS * GROUPS;       // unpack items (8 rows x 4 inputs)
   static constexpr int ITER = (ITEMS + NT - 1) / NT;
   static constexpr bool EXACT = ITEMS % NT == 0;
+  // When NT is a multiple of QUADS, all items of a thread cover the same
+  // four inputs and share one set of per-input sums.
+  static constexpr bool SHARED_Q = NT % QUADS == 0;
+  static constexpr int SUMS = SHARED_Q ? 1 : ITER;
   static constexpr int ROWB = 2 * TC;                // bytes per row and chunk
   static constexpr int BYTES = ROWS * ROWB;          // one stage buffer
+  static constexpr int GRAN = ROWB / 16;             // 16-byte granules per row and chunk
   static constexpr int KSTEPS = TC / 16;             // K=32 (16-sample) MFMA steps per chunk
-  static_assert(KSTEPS == 4 && ROWB == 128, "the unpack is split into four phases over 8 chunks per row");
+  static_assert(TC == 64 || TC == 128, "the unpack is split into four phases over the K-steps of a chunk");
   static constexpr bool FP8 = false;
 
   // Stage quad q -> first input: the first `split` quads start at base0, the
@@ -75,7 +80,11 @@ struct Stage {
     __device__ int input(int q) const { return q < split ? base0 + 4 * q : base1 + 4 * (q - split); }
   };
 
-  __device__ static int swz(int row) { return (row ^ (row >> 2)) & 7; }
+  // Granule swizzle: a bijection over any GRAN consecutive rows and over the
+  // rows 4q + c of GRAN consecutive quads q, so that fragment reads (one
+  // granule of consecutive rows) and unpack stores (one granule of every
+  // fourth row) are free of bank conflicts.
+  __device__ static int swz(int row) { return (row ^ (row >> 2)) & (GRAN - 1); }
   __device__ static bool has_item(int tid, int k) { return EXACT || tid + k * NT < ITEMS; }
 
   // Load the 8 rows x 4 inputs of this thread's items of chunk c.
@@ -94,7 +103,7 @@ struct Stage {
       // (scalar arithmetic) and whose range ends at the channel's last valid
       // row, so the per-lane offset is the same for all 8 rows of the item.
       const int rows = min(t1 - tb, TC);
-      // 64 rows of a channel span less than 2^31 bytes (checked on the host),
+      // 128 rows of a channel span less than 2^31 bytes (checked on the host),
       // so the range arithmetic stays in 32-bit scalar registers.
       const int stride32 = (int)stride;
       const int nrec0 = (rows - 1) * stride32 + p.n_inputs;
@@ -141,8 +150,9 @@ struct Stage {
   // (time-major -> input-major) and bias; phases 2/3 handle inputs 0-1 / 2-3
   // of the quad -- byte sums and one 16-byte store per input.  Two items per
   // thread: phases 0/1 transpose / store item 0, phases 2/3 item 1, so only
-  // one item's transposed words are live at a time.  Invalid codes only set
-  // `bad`; the fix-up pass zeroes those samples.
+  // one item's transposed words are live at a time.  The transposes flag
+  // invalid codes in `bad`; the item's store phase then masks them (a branch
+  // taken only by items that hold one).
   static_assert(ITER <= 2, "at most two unpack items per thread");
   static constexpr int LOAD_PHASE = ITER == 1 ? 1 : 2;  // last phase that reads the loaded words
 
@@ -157,15 +167,16 @@ struct Stage {
     for (int c = 0; c < 4; ++c) bad |= (y[2 * c + tq] - 0x11111111u) & ~y[2 * c + tq];
   }
 
-  __device__ static void store_input(const uint32_t (&y)[8], uint8_t* st, int k, int c, uint32_t (&sy)[ITER][4],
-                                     uint32_t (&sw)[ITER][4], int tid) {
+  __device__ static void store_input(const uint32_t (&y)[8], uint8_t* st, int k, int c, uint32_t (&sy)[SUMS][4],
+                                     uint32_t (&sw)[SUMS][4], int tid) {
     const int item = tid + k * NT;
     const int q = item % QUADS, g = item / QUADS;
     const int row = 4 * q + c;
     const uint32_t ya = y[2 * c], yb = y[2 * c + 1];
     const uint32_t ra = bre4(ya), ia = bim4(ya), rb = bre4(yb), ib = bim4(yb);
-    sy[k][c] = bytesum(yb, bytesum(ya, sy[k][c]));
-    sw[k][c] = bytesum(ib, bytesum(ia, sw[k][c]));
+    const int ks = SHARED_Q ? 0 : k;
+    sy[ks][c] = bytesum(yb, bytesum(ya, sy[ks][c]));
+    sw[ks][c] = bytesum(ib, bytesum(ia, sw[ks][c]));
     v4i v;
     v.x = (int)ra;
     v.y = (int)ia;
@@ -174,14 +185,22 @@ struct Stage {
     *reinterpret_cast<v4i*>(st + row * ROWB + ((g ^ swz(row)) << 4)) = v;
   }
 
+  // Rare path: some sample of the item holds the invalid code; replace each
+  // such sample by a zero sample (biased 0x88) before it is stored and summed.
+  __device__ static void mask_item(uint32_t (&y)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) y[q] = mask_invalid(y[q]);
+  }
+
   template <int PH>
   __device__ static void unpack_phase(const uint32_t (&ld)[ITER][8], uint32_t (&y)[8], uint8_t* st,
-                                      uint32_t (&sy)[ITER][4], uint32_t (&sw)[ITER][4], uint32_t& bad, int tid) {
+                                      uint32_t (&sy)[SUMS][4], uint32_t (&sw)[SUMS][4], uint32_t& bad, int tid) {
     if constexpr (ITER == 1) {
       if (!has_item(tid, 0)) return;
       if constexpr (PH < 2) {
         transpose_tq(ld, y, 0, PH, bad);
       } else {
+        if (PH == 2 && (bad & 0x88888888u)) mask_item(y);
         store_input(y, st, 0, 2 * (PH - 2), sy, sw, tid);
         store_input(y, st, 0, 2 * (PH - 2) + 1, sy, sw, tid);
       }
@@ -192,63 +211,21 @@ struct Stage {
         transpose_tq(ld, y, k, 0, bad);
         transpose_tq(ld, y, k, 1, bad);
       } else {
+        if (bad & 0x88888888u) mask_item(y);
+        bad = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) store_input(y, st, k, c, sy, sw, tid);
       }
     }
   }
 
-  __device__ static void unpack_all(const uint32_t (&ld)[ITER][8], uint8_t* st, uint32_t (&sy)[ITER][4],
-                                    uint32_t (&sw)[ITER][4], uint32_t& bad, int tid) {
+  __device__ static void unpack_all(const uint32_t (&ld)[ITER][8], uint8_t* st, uint32_t (&sy)[SUMS][4],
+                                    uint32_t (&sw)[SUMS][4], uint32_t& bad, int tid) {
     uint32_t y[8];
     unpack_phase<0>(ld, y, st, sy, sw, bad, tid);
     unpack_phase<1>(ld, y, st, sy, sw, bad, tid);
     unpack_phase<2>(ld, y, st, sy, sw, bad, tid);
     unpack_phase<3>(ld, y, st, sy, sw, bad, tid);
-  }
-
-  // Rare path: replace every invalid sample of a stage buffer (a biased part
-  // of 0, i.e. the code 8) by a zero sample (u = w = 8) and correct the
-  // per-input sums.
-  __device__ static void fixup_invalid(uint8_t* st, uint32_t* s_sy, uint32_t* s_sw, int tid) {
-    for (int gi = tid; gi < BYTES / 8; gi += NT) {
-      uint2* gp = reinterpret_cast<uint2*>(st) + gi;
-      uint2 v = *gp;
-      const uint32_t ok = (v.x + 0x7F7F7F7Fu) & (v.y + 0x7F7F7F7Fu) & 0x80808080u;
-      if (ok == 0x80808080u) continue;
-      const int row = (gi * 8) / ROWB;
-      uint32_t dy = 0, dw = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if ((ok >> (8 * b + 7)) & 1u) continue;
-        const uint32_t u = (v.x >> (8 * b)) & 0xFFu, w = (v.y >> (8 * b)) & 0xFFu;
-        dy += 136u - (16u * u + w);
-        dw += 8u - w;
-        v.x = (v.x & ~(0xFFu << (8 * b))) | (8u << (8 * b));
-        v.y = (v.y & ~(0xFFu << (8 * b))) | (8u << (8 * b));
-      }
-      *gp = v;
-      atomicAdd(&s_sy[row], dy);
-      atomicAdd(&s_sw[row], dw);
-    }
-  }
-
-  // End of an unpack: raise the (workgroup-wide) flag of stage buffer `slot`
-  // if any lane saw an invalid code.
-  __device__ static void publish_bad(uint32_t bad, uint32_t* s_bad, int slot, int tid) {
-    if (__any((bad & 0x88888888u) != 0u) && (tid & 63) == 0) s_bad[slot] = 1u;
-  }
-
-  // After the barrier that ends an unpack: fix the stage buffer if flagged.
-  // The flag is shared by all thread groups of the workgroup, so every group
-  // takes the same branch and the barriers inside stay matched.
-  __device__ static void check_bad(uint8_t* st, uint32_t* s_bad, int slot, uint32_t* s_sy, uint32_t* s_sw, int tid) {
-    if (s_bad[slot]) {
-      fixup_invalid(st, s_sy, s_sw, tid);
-      __syncthreads();
-      if (tid == 0) s_bad[slot] = 0u;
-      __syncthreads();
-    }
   }
 
   __device__ static v4i read_frag(const uint8_t* st, int row, int chunk) {
@@ -257,10 +234,10 @@ struct Stage {
 
   // Reduce the per-thread sums into s_sy / s_sw, then turn them into the
   // correction terms e_k = Sy_k + 30 Sw_k and g_k = Sy_k - 2 Sw_k in place.
-  __device__ static void finish_sums(const uint32_t (&sy)[ITER][4], const uint32_t (&sw)[ITER][4], uint32_t* s_sy,
+  __device__ static void finish_sums(const uint32_t (&sy)[SUMS][4], const uint32_t (&sw)[SUMS][4], uint32_t* s_sy,
                                      uint32_t* s_sw, int tid) {
 #pragma unroll
-    for (int k = 0; k < ITER; ++k) {
+    for (int k = 0; k < SUMS; ++k) {
       if (!has_item(tid, k)) continue;
       const int q = (tid + k * NT) % QUADS;
 #pragma unroll
@@ -332,18 +309,16 @@ __device__ inline void write_out(int2* out, const int64_t (&pos)[UN], const bool
 // the chunk after that issued once the registers are free.
 template <class S, bool ALIGNED, class KStep>
 __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, int f, int t0, int t1, int64_t stride,
-                                  int tid, uint8_t* lds, uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad,
-                                  uint32_t (&sy)[S::ITER][4], uint32_t (&sw)[S::ITER][4], int nchunks, KStep&& kstep) {
+                                  int tid, uint8_t* lds,
+                                  uint32_t (&sy)[S::SUMS][4], uint32_t (&sw)[S::SUMS][4], int nchunks, KStep&& kstep) {
   uint32_t ld[S::ITER][8];
   if (nchunks > 0) {
     uint32_t bad = 0;
     S::template load<ALIGNED>(p, m, f, t0, t1, 0, stride, tid, ld);
     S::unpack_all(ld, lds, sy, sw, bad, tid);
-    S::publish_bad(bad, s_bad, 0, tid);
     if (nchunks > 1) S::template load<ALIGNED>(p, m, f, t0, t1, 1, stride, tid, ld);
   }
   __syncthreads();
-  if (nchunks > 0) S::check_bad(lds, s_bad, 0, s_sy, s_sw, tid);
 
   auto step = [&](int c, auto more1, auto more2) {
     constexpr bool M1 = decltype(more1)::value, M2 = decltype(more2)::value;
@@ -366,9 +341,7 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
           S::template load<ALIGNED>(p, m, f, t0, t1, c + 2, stride, tid, ld);
       }
     }
-    if constexpr (M1) S::publish_bad(bad, s_bad, (c + 1) & 1, tid);
     __syncthreads();
-    if constexpr (M1) S::check_bad(nst, s_bad, (c + 1) & 1, s_sy, s_sw, tid);
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
@@ -383,6 +356,12 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
 
 // ---- diagonal unit -----------------------------------------------------------
 
+// Samples per chunk of a diagonal unit.  (128 would halve the barriers per
+// sample, but the extra loads in flight exceed the registers of two waves
+// per SIMD.)
+template <int NB>
+constexpr int diag_tc = 64;
+
 template <int NB, int WC>
 struct DiagGeom {
   static constexpr int WR = 2;                       // wave rows
@@ -395,7 +374,8 @@ struct DiagGeom {
   static constexpr int H = NB / 2;                   // quadrant side
   static constexpr int XPITCH = H + 1;
   static constexpr int XAREA = H * XPITCH;           // int32 words of one exchange area
-  static constexpr int STAGE = NB * 128;             // one stage buffer (TC = 64)
+  static constexpr int TC = diag_tc<NB>;             // samples per chunk
+  static constexpr int STAGE = NB * 2 * TC;          // one stage buffer
   static constexpr int LDS = (2 * STAGE > 2 * XAREA * 4) ? 2 * STAGE : 2 * XAREA * 4;
   static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tiles are made of 32x32 MFMA tiles");
   static_assert(WC % 2 == 0, "quadrants are made of whole wave tiles");
@@ -444,26 +424,25 @@ __device__ inline void combine_quadrant(const Problem& p, int f, int ibase, cons
 
 // One diagonal unit: inputs ibase .. ibase+NB-1 of channel f over samples
 // [t0, t1), run by the NT threads whose local index is tid.  lds: G::LDS
-// bytes; s_sy, s_sw: NB words each; s_bad: 2 words shared by the workgroup.
+// bytes; s_sy, s_sw: NB words each.
 template <int NB, int WC, bool ALIGNED>
 __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int tid, uint8_t* lds, uint32_t* s_sy,
-                         uint32_t* s_sw, uint32_t* s_bad, int mode) {
+                         uint32_t* s_sw, int mode) {
   // Values derived from the thread index are recomputed for every unit: when
   // units run in a loop (the persistent kernel), hoisting them out of it would
   // keep them live across the whole unit and exhaust the registers.
   asm volatile("" : "+v"(tid));
   using G = DiagGeom<NB, WC>;
-  using S = Stage<NB, 64, G::NT>;
+  using S = Stage<NB, G::TC, G::NT>;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WC, wc = wave % WC;
-  const int nchunks = t1 > t0 ? (t1 - t0 + 63) / 64 : 0;
+  const int nchunks = t1 > t0 ? (t1 - t0 + G::TC - 1) / G::TC : 0;
   const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
 
   for (int k = tid; k < NB; k += G::NT) {
     s_sy[k] = 0;
     s_sw[k] = 0;
   }
-  if (tid < 2) s_bad[tid] = 0;
   __syncthreads();
 
   v16i acc[G::FM][G::FN];
@@ -471,16 +450,16 @@ __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int
   for (int x = 0; x < G::FM; ++x)
 #pragma unroll
     for (int z = 0; z < G::FN; ++z) acc[x][z] = v16i{0};
-  uint32_t sy[S::ITER][4], sw[S::ITER][4];
+  uint32_t sy[S::SUMS][4], sw[S::SUMS][4];
 #pragma unroll
-  for (int k = 0; k < S::ITER; ++k)
+  for (int k = 0; k < S::SUMS; ++k)
 #pragma unroll
     for (int c = 0; c < 4; ++c) sy[k][c] = sw[k][c] = 0;
 
   const int half = lane >> 5;
   const int rrow = wr * G::TM + (lane & 31), crow = wc * G::TN + (lane & 31);
   const typename S::Map m{ibase, NB / 4, ibase};
-  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, s_bad, sy, sw, nchunks,
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, sy, sw, nchunks,
                          [&](const uint8_t* st, int ks) {
                            v4i a[G::FM], b[G::FN];
 #pragma unroll
@@ -496,7 +475,7 @@ __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int
                          });
 
   S::finish_sums(sy, sw, s_sy, s_sw, tid);
-  const uint32_t tproc = (uint32_t)(nchunks * 64);
+  const uint32_t tproc = (uint32_t)(nchunks * G::TC);
   int* xa = reinterpret_cast<int*>(lds);
   int* xb = xa + G::XAREA;
   constexpr int HW = WC / 2;  // wave columns per quadrant
@@ -527,7 +506,7 @@ struct PairGeom {
 
 template <bool ALIGNED>
 __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1, int tid, uint8_t* lds,
-                         uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+                         uint32_t* s_sy, uint32_t* s_sw, int mode) {
   // Values derived from the thread index are recomputed for every unit: when
   // units run in a loop (the persistent kernel), hoisting them out of it would
   // keep them live across the whole unit and exhaust the registers.
@@ -542,7 +521,6 @@ __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1
     s_sy[k] = 0;
     s_sw[k] = 0;
   }
-  if (tid < 2) s_bad[tid] = 0;
   __syncthreads();
 
   v16i c1[2][2], hm[2][2];
@@ -550,16 +528,16 @@ __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int z = 0; z < 2; ++z) c1[x][z] = hm[x][z] = v16i{0};
-  uint32_t sy[S::ITER][4], sw[S::ITER][4];
+  uint32_t sy[S::SUMS][4], sw[S::SUMS][4];
 #pragma unroll
-  for (int k = 0; k < S::ITER; ++k)
+  for (int k = 0; k < S::SUMS; ++k)
 #pragma unroll
     for (int c = 0; c < 4; ++c) sy[k][c] = sw[k][c] = 0;
 
   const int half = lane >> 5;
   const int irow = wr * 64 + (lane & 31), jrow = 128 + wc * 64 + (lane & 31);
   const typename S::Map m{I0, 32, J0};
-  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, s_bad, sy, sw, nchunks,
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, sy, sw, nchunks,
                          [&](const uint8_t* st, int ks) {
                            v4i ai[2], bi[2], aj[2], bj[2];
 #pragma unroll
@@ -629,6 +607,7 @@ __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1
 template <int ROWS, int NT>
 struct StageF8 {
   using L = Stage<ROWS, 64, NT>;  // same loads and item geometry as int8
+  static constexpr int SUMS = L::SUMS;
   static constexpr int QUADS = L::QUADS;
   static constexpr int ITER = L::ITER;
   static constexpr int ROWB = 128;
@@ -670,7 +649,7 @@ struct StageF8 {
   // of A and one of B per input.
   template <int PH>
   __device__ static void unpack_phase(const uint32_t (&ld)[ITER][8], uint32_t (&y)[8], uint8_t* st,
-                                      uint32_t (&)[ITER][4], uint32_t (&)[ITER][4], uint32_t& bad, int tid) {
+                                      uint32_t (&)[SUMS][4], uint32_t (&)[SUMS][4], uint32_t& bad, int tid) {
     if (!L::has_item(tid, 0)) return;
     if constexpr (PH < 2) {
       L::transpose_tq(ld, y, 0, PH, bad);
@@ -699,8 +678,8 @@ struct StageF8 {
     }
   }
 
-  __device__ static void unpack_all(const uint32_t (&ld)[ITER][8], uint8_t* st, uint32_t (&sy)[ITER][4],
-                                    uint32_t (&sw)[ITER][4], uint32_t& bad, int tid) {
+  __device__ static void unpack_all(const uint32_t (&ld)[ITER][8], uint8_t* st, uint32_t (&sy)[SUMS][4],
+                                    uint32_t (&sw)[SUMS][4], uint32_t& bad, int tid) {
     uint32_t y[8];
     unpack_phase<0>(ld, y, st, sy, sw, bad, tid);
     unpack_phase<1>(ld, y, st, sy, sw, bad, tid);
@@ -709,8 +688,6 @@ struct StageF8 {
   }
 
   // Invalid samples are zeroed during the unpack: nothing to publish or fix.
-  __device__ static void publish_bad(uint32_t, uint32_t*, int, int) {}
-  __device__ static void check_bad(uint8_t*, uint32_t*, int, uint32_t*, uint32_t*, int) {}
 
   // 32 bytes (16 samples) of one input for a K=64 step; `part` = 2 ks + half.
   __device__ static v8i read_frag(const uint8_t* arr, int row, int part) {
@@ -724,7 +701,7 @@ struct StageF8 {
 // One fp8 diagonal unit of 256 inputs (inputs ibase ..), 8 waves.
 template <bool ALIGNED>
 __device__ void run_diag_f8(const Problem& p, int f, int ibase, int t0, int t1, int tid, uint8_t* lds,
-                            uint32_t* s_sy, uint32_t* s_sw, uint32_t* s_bad, int mode) {
+                            uint32_t* s_sy, uint32_t* s_sw, int mode) {
   // Values derived from the thread index are recomputed for every unit: when
   // units run in a loop (the persistent kernel), hoisting them out of it would
   // keep them live across the whole unit and exhaust the registers.
@@ -741,7 +718,6 @@ __device__ void run_diag_f8(const Problem& p, int f, int ibase, int t0, int t1, 
     s_sy[k] = 0;  // no correction terms in the unbiased formulation
     s_sw[k] = 0;
   }
-  if (tid < 2) s_bad[tid] = 0;
   __syncthreads();
 
   v16f acc[G::FM][G::FN];
@@ -754,7 +730,7 @@ __device__ void run_diag_f8(const Problem& p, int f, int ibase, int t0, int t1, 
   const int half = lane >> 5;
   const int rrow = wr * G::TM + (lane & 31), crow = wc * G::TN + (lane & 31);
   const typename S::Map m{ibase, 64, ibase};
-  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, s_bad, sy, sw, nchunks,
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, sy, sw, nchunks,
                          [&](const uint8_t* st, int ks) {
                            v8i a[G::FM], b[G::FN];
 #pragma unroll
@@ -816,13 +792,13 @@ __global__ __launch_bounds__(128 * WC, unit_min_blocks<128 * WC>) void xmac_diag
   using G = DiagGeom<NB, WC>;
   static_assert(G::NT == 128 * WC, "thread count must match the launch bounds");
   __shared__ __attribute__((aligned(16))) uint8_t lds[G::LDS];
-  __shared__ uint32_t s_sy[NB], s_sw[NB], s_bad[2];
+  __shared__ uint32_t s_sy[NB], s_sw[NB];
   int u = xcd_remap(blockIdx.x, gridDim.x);
   const int sp = u % nsplit;
   u /= nsplit;
   const int blk = u % nblk, f = u / nblk;
   const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
-  run_diag<NB, WC, ALIGNED>(p, f, blk * NB, t0, t1, threadIdx.x, lds, s_sy, s_sw, s_bad,
+  run_diag<NB, WC, ALIGNED>(p, f, blk * NB, t0, t1, threadIdx.x, lds, s_sy, s_sw,
                             nsplit > 1 ? (int)kWriteAtomic : mode);
 }
 
@@ -840,7 +816,7 @@ __device__ inline void pair_decode(int pu, int& I0, int& J0) {
 template <bool ALIGNED>
 __global__ __launch_bounds__(512, 1) void xmac_pair_i8(Problem p, int npair, int nsplit, int tsplit, int mode) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[PairGeom::LDS];
-  __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS], s_bad[2];
+  __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS];
   int u = xcd_remap(blockIdx.x, gridDim.x);
   const int sp = u % nsplit;
   u /= nsplit;
@@ -848,24 +824,24 @@ __global__ __launch_bounds__(512, 1) void xmac_pair_i8(Problem p, int npair, int
   int I0, J0;
   pair_decode(pu, I0, J0);
   const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
-  run_pair<ALIGNED>(p, f, I0, J0, t0, t1, threadIdx.x, lds, s_sy, s_sw, s_bad, nsplit > 1 ? (int)kWriteAtomic : mode);
+  run_pair<ALIGNED>(p, f, I0, J0, t0, t1, threadIdx.x, lds, s_sy, s_sw, nsplit > 1 ? (int)kWriteAtomic : mode);
 }
 
 template <bool ALIGNED>
 __global__ __launch_bounds__(512, 1) void xmac_diag_f8(Problem p, int nsplit, int tsplit, int mode) {
   using G = DiagGeom<256, 4>;
   __shared__ __attribute__((aligned(16))) uint8_t lds[G::LDS];
-  __shared__ uint32_t s_sy[256], s_sw[256], s_bad[2];
+  __shared__ uint32_t s_sy[256], s_sw[256];
   int u = xcd_remap(blockIdx.x, gridDim.x);
   const int sp = u % nsplit, f = u / nsplit;
   const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
-  run_diag_f8<ALIGNED>(p, f, 0, t0, t1, threadIdx.x, lds, s_sy, s_sw, s_bad, nsplit > 1 ? (int)kWriteAtomic : mode);
+  run_diag_f8<ALIGNED>(p, f, 0, t0, t1, threadIdx.x, lds, s_sy, s_sw, nsplit > 1 ? (int)kWriteAtomic : mode);
 }
 
 static bool aligned_problem(const Problem& p) {
   const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
   return (p.n_inputs % 4 == 0) && ((reinterpret_cast<uintptr_t>(p.in) & 3) == 0) &&
-         64 * stride + p.n_inputs < 0x7FFFFFFF;
+         128 * stride + p.n_inputs < 0x7FFFFFFF;
 }
 
 template <int NB, int WC>
@@ -961,7 +937,7 @@ __device__ inline WorkItem batch_item(const WorkItem* items, int it) {
 template <int NB>
 __device__ __noinline__ int batch_small_run(const Problem* table, const WorkItem* items, int n_items, int* counter,
                                             int it, int base_mode, uint8_t* lds, uint32_t* s_sy, uint32_t* s_sw,
-                                            uint32_t* s_bad, int* s_item) {
+                                            int* s_item) {
   constexpr int kind = NB == 64 ? kUnitDiag64x2 : kUnitDiag128x2;
   while (it < n_items) {
     const WorkItem w = batch_item(items, it);
@@ -971,7 +947,7 @@ __device__ __noinline__ int batch_small_run(const Problem* table, const WorkItem
     const int tid = threadIdx.x;
     const int g = tid >> 8, f = w.channel + g;
     run_diag<NB, 2, true>(p, min(f, p.n_chan - 1), 0, w.t0, w.t1, tid & 255, lds + g * DiagGeom<NB, 2>::LDS,
-                          s_sy + NB * g, s_sw + NB * g, s_bad, f < p.n_chan ? mode : (int)kWriteNone);
+                          s_sy + NB * g, s_sw + NB * g, f < p.n_chan ? mode : (int)kWriteNone);
     it = batch_fetch(counter, s_item);
   }
   return it;
@@ -983,7 +959,7 @@ __device__ __noinline__ int batch_small_run(const Problem* table, const WorkItem
 __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const WorkItem* items, int n_items,
                                                          int* counter, int base_mode) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kBatchLds];
-  __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS], s_bad[2];
+  __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS];
   __shared__ int s_item;
   const int tid = threadIdx.x;
   // The problem table is the first kernel argument: read it in place in the
@@ -995,21 +971,21 @@ __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const Wo
   while (it < n_items) {
     const WorkItem w = batch_item(items, it);
     if (w.kind == kUnitDiag64x2) {
-      it = batch_small_run<64>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, s_bad, &s_item);
+      it = batch_small_run<64>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
       continue;
     }
     if (w.kind == kUnitDiag128x2) {
-      it = batch_small_run<128>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, s_bad, &s_item);
+      it = batch_small_run<128>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
       continue;
     }
     const Problem p = table[w.array];
     const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
     if (w.kind == kUnitDiag256) {
-      run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
+      run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, tid, lds, s_sy, s_sw, mode);
     } else {
       int I0, J0;
       pair_decode(w.tile, I0, J0);
-      run_pair<true>(p, w.channel, I0, J0, w.t0, w.t1, tid, lds, s_sy, s_sw, s_bad, mode);
+      run_pair<true>(p, w.channel, I0, J0, w.t0, w.t1, tid, lds, s_sy, s_sw, mode);
     }
     it = batch_fetch(counter, &s_item);
   }
