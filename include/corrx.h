@@ -143,6 +143,57 @@ int corr_xmac(corrx_t h, const void *in, void *acc, void *stream);
  */
 int corr_dump(corrx_t h, const void *acc, int order, int dtype, void *dst, void *stream);
 
+/*
+ * corr_dump with channel averaging (Sec. 3.4.3: the archived products may be
+ * averaged by two in time and in frequency).  Time averaging is done by
+ * accumulating t_avg integrations into acc before the dump; this call sums
+ * f_avg adjacent channels: output channel g = channels g*f_avg .. g*f_avg +
+ * f_avg - 1, in the given order.  CORRX_I32 writes the integer sum;
+ * CORRX_F32 writes sum / (f_avg * t_avg), exact because both factors must be
+ * powers of two (f_avg dividing n_chan, f_avg * t_avg <= 4096) and the sum is
+ * checked to stay within 2^24 (CORRX_EOVERFLOW otherwise).  dst: device,
+ * corr_dump_count(h, order) / f_avg values of 4 bytes; must not overlap acc.
+ */
+int corr_dump_avg(corrx_t h, const void *acc, int order, int dtype, int f_avg, int t_avg, void *dst,
+                  void *stream);
+
+/* ---- PFB packet order (Appendix A, B, C) ------------------------------- */
+
+/*
+ * Input order of the X-engine buffer built from PFB packets.  PACKET keeps the
+ * order of the antenna samples inside a packet, as the paper's XMAC servers
+ * do (input 64 b + k for position k of PFB b); NATURAL undoes the PFB's
+ * permutation on the way in (position k holds PFB input 16 (k % 4) + k / 4,
+ * Appendix A), so input 64 b + a is PFB b's input a.
+ */
+enum { CORRX_ORDER_PACKET = 0, CORRX_ORDER_NATURAL = 1 };
+
+/*
+ * Corner turn of PFB lane payloads into the handle's input buffer (layout
+ * TFI; n_inputs = 64 per PFB, at most 4 PFBs; n_chan a multiple of 128, i.e.
+ * whole coarse channels).  lanes: HOST array of 8 * n_pfb DEVICE pointers
+ * (16-byte aligned), lane (PFB b, fibre n) at index 8 b + n.  Each lane buffer
+ * holds that lane's packet payloads (header, counters and checksum removed)
+ * for the handle's coarse channels in stream order (Appendix A): packet
+ * (c, s, t) at byte offset ((c * 4 + s) * n_time + t) * 256 for coarse
+ * channel c, group s (0..3) and time t, and inside a packet byte 64 f2 + k is
+ * fine channel f2 (0..3) of position k (0..63).  That byte becomes sample
+ * (time t, channel 128 c + 16 n + 4 s + f2, input per `order`) of `in`
+ * (device, 16-byte aligned, n_time * n_chan * n_inputs bytes).
+ */
+int corr_pfb_ingest(corrx_t h, const void *const *lanes, int order, void *in, void *stream);
+
+/*
+ * Remap visibilities correlated in PACKET order to NATURAL order (Appendix C,
+ * "GPU Output": products of permuted inputs, some of them conjugated).  For
+ * natural inputs i >= j at packet indices P(i), P(j) (P(64 b + a) = 64 b +
+ * 4 (a % 16) + a / 16): acc_nat[f][i][j] = acc_pkt[f][P(i)][P(j)] if
+ * P(i) >= P(j), else its conjugate taken from acc_pkt[f][P(j)][P(i)].  Both
+ * are device accumulators of the handle's shape (corr_acc_bytes, 8-byte
+ * aligned, not overlapping); n_inputs must be a multiple of 64.
+ */
+int corr_pfb_remap(corrx_t h, const void *acc_pkt, void *acc_nat, void *stream);
+
 /* Samples accumulated since the last corr_zero (host-side count). */
 int64_t corr_samples(corrx_t h);
 

@@ -38,6 +38,8 @@ CORRX_TILE_DEFAULT = 0
 CORRX_TILE_UNIT64 = 1
 CORRX_TILE_UNIT128 = 2
 CORRX_TILE_UNIT256 = 3
+CORRX_ORDER_PACKET = 0
+CORRX_ORDER_NATURAL = 1
 
 ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
            "mfma_i8": CORRX_ENGINE_MFMA_I8, "mfma_f8": CORRX_ENGINE_MFMA_F8}
@@ -45,7 +47,8 @@ ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
 # Exported symbols, in header order.
 SYMBOLS = ("corr_abi_version", "corr_strerror", "corr_create", "corr_destroy", "corr_set_engine",
            "corr_get_engine", "corr_acc_bytes", "corr_dump_count", "corr_zero", "corr_xmac",
-           "corr_dump", "corr_samples", "corr_beam", "corr_batch_create", "corr_batch_destroy",
+           "corr_dump", "corr_dump_avg", "corr_pfb_ingest", "corr_pfb_remap", "corr_samples",
+           "corr_beam", "corr_batch_create", "corr_batch_destroy",
            "corr_batch_items", "corr_batch_plan", "corr_batch_zero", "corr_batch_xmac")
 
 
@@ -84,6 +87,9 @@ def lib() -> ctypes.CDLL:
             "corr_zero": ([vp, vp, vp], i),
             "corr_xmac": ([vp, vp, vp, vp], i),
             "corr_dump": ([vp, vp, i, i, vp, vp], i),
+            "corr_dump_avg": ([vp, vp, i, i, i, i, vp, vp], i),
+            "corr_pfb_ingest": ([vp, ctypes.POINTER(vp), i, vp, vp], i),
+            "corr_pfb_remap": ([vp, vp, vp, vp], i),
             "corr_samples": ([vp], i64),
             "corr_beam": ([vp, vp, vp, vp], i),
             "corr_batch_create": ([ctypes.POINTER(corrx_desc), i, i, ctypes.POINTER(ctypes.c_int),
@@ -172,6 +178,21 @@ def corr_xmac(h: int, inp, acc, stream=None) -> None:
 
 def corr_dump(h: int, acc, order: int, dtype: int, dst, stream=None) -> None:
     _check(lib().corr_dump(h, _ptr(acc), order, dtype, _ptr(dst), _stream(stream)), "corr_dump")
+
+
+def corr_dump_avg(h: int, acc, order: int, dtype: int, f_avg: int, t_avg: int, dst, stream=None) -> None:
+    _check(lib().corr_dump_avg(h, _ptr(acc), order, dtype, f_avg, t_avg, _ptr(dst), _stream(stream)),
+           "corr_dump_avg")
+
+
+def corr_pfb_ingest(h: int, lanes, order: int, inp, stream=None) -> None:
+    n = len(lanes)
+    pl = (ctypes.c_void_p * n)(*[_ptr(x) for x in lanes])
+    _check(lib().corr_pfb_ingest(h, pl, order, _ptr(inp), _stream(stream)), "corr_pfb_ingest")
+
+
+def corr_pfb_remap(h: int, acc_pkt, acc_nat, stream=None) -> None:
+    _check(lib().corr_pfb_remap(h, _ptr(acc_pkt), _ptr(acc_nat), _stream(stream)), "corr_pfb_remap")
 
 
 def corr_beam(h: int, inp, out, stream=None) -> None:
@@ -264,6 +285,28 @@ class Correlator:
                               device=acc.device)
         corr_dump(self.h, acc, order, dtype, dst, stream)
         return dst
+
+    def dump_avg(self, acc, f_avg: int, t_avg: int = 1, order: int = CORRX_TRI_STATION_POL,
+                 dtype: int = CORRX_F32, dst=None, stream=None):
+        n = corr_dump_count(self.h, order) // f_avg
+        if dst is None:
+            dst = torch.empty(n, dtype=torch.int32 if dtype == CORRX_I32 else torch.float32,
+                              device=acc.device)
+        corr_dump_avg(self.h, acc, order, dtype, f_avg, t_avg, dst, stream)
+        return dst
+
+    def pfb_ingest(self, lanes, order: int = CORRX_ORDER_NATURAL, inp=None, stream=None):
+        if inp is None:
+            inp = torch.empty(self.n_time * self.n_chan * self.n_inputs, dtype=torch.uint8,
+                              device=lanes[0].device)
+        corr_pfb_ingest(self.h, lanes, order, inp, stream)
+        return inp
+
+    def pfb_remap(self, acc_pkt, acc_nat=None, stream=None):
+        if acc_nat is None:
+            acc_nat = torch.empty_like(acc_pkt)
+        corr_pfb_remap(self.h, acc_pkt, acc_nat, stream)
+        return acc_nat
 
     def beam(self, inp, out=None, stream=None):
         if out is None:

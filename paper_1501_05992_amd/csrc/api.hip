@@ -171,7 +171,56 @@ int corr_dump(corrx_t h, const void* acc, int order, int dtype, void* dst, void*
   const char* d = static_cast<const char*>(dst);
   const size_t na = corr_acc_bytes(h), nd = corr_dump_count(h, order) * 4;
   if (a < d + nd && d < a + na) return CORRX_EINVAL;
-  return launch_dump(static_cast<const int*>(acc), h->n_inputs, h->n_chan, order, dtype, dst, as_stream(stream));
+  return launch_dump(static_cast<const int*>(acc), h->n_inputs, h->n_chan, order, dtype, 1, 1.0f, dst,
+                     as_stream(stream));
+}
+
+int corr_dump_avg(corrx_t h, const void* acc, int order, int dtype, int f_avg, int t_avg, void* dst, void* stream) {
+  if (!h || !acc || !dst) return CORRX_EINVAL;
+  if (order != CORRX_TRI_INPUT && order != CORRX_TRI_STATION_POL) return CORRX_EINVAL;
+  if (dtype != CORRX_I32 && dtype != CORRX_F32) return CORRX_EINVAL;
+  if (order == CORRX_TRI_STATION_POL && h->n_inputs % 2) return CORRX_EINVAL;
+  if (f_avg < 1 || (f_avg & (f_avg - 1)) || h->n_chan % f_avg) return CORRX_EINVAL;
+  if (t_avg < 1 || (t_avg & (t_avg - 1)) || (int64_t)f_avg * t_avg > 4096) return CORRX_EINVAL;
+  // Integer sums of f_avg channels stay exact in int32, and in float32 while
+  // |sum| <= 98 * samples * f_avg <= 2^24.
+  if (h->samples * f_avg > kMaxAccSamples) return CORRX_EOVERFLOW;
+  if (dtype == CORRX_F32 && h->samples * f_avg > kMaxF32Samples) return CORRX_EOVERFLOW;
+  const char* a = static_cast<const char*>(acc);
+  const char* d = static_cast<const char*>(dst);
+  const size_t na = corr_acc_bytes(h), nd = corr_dump_count(h, order) / f_avg * 4;
+  if (a < d + nd && d < a + na) return CORRX_EINVAL;
+  return launch_dump(static_cast<const int*>(acc), h->n_inputs, h->n_chan, order, dtype, f_avg,
+                     1.0f / (float)(f_avg * t_avg), dst, as_stream(stream));
+}
+
+int corr_pfb_ingest(corrx_t h, const void* const* lanes, int order, void* in, void* stream) {
+  if (!h || !lanes || !in) return CORRX_EINVAL;
+  if (order != CORRX_ORDER_PACKET && order != CORRX_ORDER_NATURAL) return CORRX_EINVAL;
+  if (h->layout != CORRX_LAYOUT_TFI || h->n_inputs % 64 || h->n_inputs > 256 || h->n_chan % 128)
+    return CORRX_EUNSUPPORTED;
+  if (reinterpret_cast<uintptr_t>(in) & 15) return CORRX_EINVAL;
+  const int n_pfb = h->n_inputs / 64;
+  PfbLanes pl;
+  memset(&pl, 0, sizeof(pl));
+  for (int k = 0; k < 8 * n_pfb; ++k) {
+    if (!lanes[k] || (reinterpret_cast<uintptr_t>(lanes[k]) & 15)) return CORRX_EINVAL;
+    pl.p[k] = static_cast<const uint8_t*>(lanes[k]);
+  }
+  return launch_pfb_ingest(pl, static_cast<uint8_t*>(in), n_pfb, h->n_chan / 128, h->n_time,
+                           order == CORRX_ORDER_NATURAL, as_stream(stream));
+}
+
+int corr_pfb_remap(corrx_t h, const void* acc_pkt, void* acc_nat, void* stream) {
+  if (!h || !acc_pkt || !acc_nat) return CORRX_EINVAL;
+  if (h->n_inputs % 64) return CORRX_EUNSUPPORTED;
+  if ((reinterpret_cast<uintptr_t>(acc_pkt) & 7) || (reinterpret_cast<uintptr_t>(acc_nat) & 7)) return CORRX_EINVAL;
+  const char* a = static_cast<const char*>(acc_pkt);
+  const char* d = static_cast<const char*>(acc_nat);
+  const size_t na = corr_acc_bytes(h);
+  if (a < d + na && d < a + na) return CORRX_EINVAL;
+  return launch_pfb_remap(static_cast<const int*>(acc_pkt), static_cast<int*>(acc_nat), h->n_inputs, h->n_chan,
+                          as_stream(stream));
 }
 
 int corr_beam(corrx_t h, const void* in, void* out, void* stream) {

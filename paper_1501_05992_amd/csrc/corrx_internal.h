@@ -126,7 +126,16 @@ int mfma_units_per_channel(int n_inputs);
 int launch_plain(const Problem& p, int nsplit, int mode, hipStream_t s);
 // accumulator fill, dump and incoherent beam.
 int launch_zero(int* acc, int64_t n_words, hipStream_t s);
-int launch_dump(const int* acc, int n_inputs, int n_chan, int order, int dtype, void* dst, hipStream_t s);
+int launch_dump(const int* acc, int n_inputs, int n_chan, int order, int dtype, int f_avg, float scale, void* dst,
+                hipStream_t s);
+
+// Lane payload pointers of up to four PFBs (8 lanes each), passed by value.
+struct PfbLanes {
+  const uint8_t* p[32];
+};
+int launch_pfb_ingest(const PfbLanes& lanes, uint8_t* out, int n_pfb, int n_coarse, int n_time, int natural,
+                      hipStream_t s);
+int launch_pfb_remap(const int* src, int* dst, int n_inputs, int n_chan, hipStream_t s);
 int launch_beam(const Problem& p, int* out, hipStream_t s);
 
 // ---- persistent batched engine ---------------------------------------------

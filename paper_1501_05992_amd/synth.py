@@ -127,6 +127,22 @@ def make_input(seed: int, n_inputs: int, n_chan: int, n_time: int, layout: int =
     return out
 
 
+def lane_payloads(seed: int, n_pfb: int, n_coarse: int, n_time: int) -> list[np.ndarray]:
+    """Packet payloads of the 8 * n_pfb PFB lanes (lane of PFB b, fibre n at
+    index 8 b + n): n_coarse * 4 * n_time packets of 256 packed samples each,
+    seeded noise of RMS 2.5 per part, clipped to [-7, 7]; one Philox stream per
+    lane.  Only draws samples; their order inside a lane is the caller's."""
+    out = []
+    n = n_coarse * 4 * n_time * 256
+    for lane in range(8 * n_pfb):
+        rng = _rng(seed, 1000 + lane, 0)
+        z = rng.standard_normal((n, 2), dtype=np.float32) * np.float32(SIGMA)
+        re = np.clip(np.rint(z[:, 0]), -7, 7).astype(np.int8)
+        im = np.clip(np.rint(z[:, 1]), -7, 7).astype(np.int8)
+        out.append((((re.astype(np.uint8) & 0xF) << 4) | (im.astype(np.uint8) & 0xF)).astype(np.uint8))
+    return out
+
+
 def tone_input(gains_re: np.ndarray, gains_im: np.ndarray, n_chan: int, n_time: int,
                layout: int = LAYOUT_TFI) -> np.ndarray:
     """Single injected tone x_i(t) = g_i * j**t, identical in every channel.
