@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--n-time", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-engine and small-config lines")
-    ap.add_argument("--cpu-channels", type=int, default=256, help="channels in the oracle's timed sample")
+    ap.add_argument("--cpu-channels", type=int, default=768, help="channels in the oracle's timed sample")
     ap.add_argument("--check-channels", type=int, default=2, help="channels checked against the oracle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one 1 GiB device-to-device copy (calibrates traffic counters)")
@@ -260,8 +260,65 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
         c.close()
     del x2
     out["uneven_batch"] = uneven_batch(corrx, model, synth, torch, dev, oracle)
+    out["pfb_and_output"] = pfb_and_output(corrx, torch, dev, x, n, fc, tc)
     out["streaming"] = streaming(synth, torch)
     return out
+
+
+def time_ms(torch, fn, reps):
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(s)
+        fn()
+        b.record(s)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def pfb_and_output(corrx, torch, dev, x, n, fc, tc):
+    """Steps on either side of the X-engine at the full band, all HBM-bound:
+    PFB packet-order ingest (the 7.86 GB input buffer reused as the 32 lane
+    payloads: 32 x 24 coarse x 4 groups x 10000 samples x 256 bytes), the
+    product remap to natural order, and the 2x2-averaged paper-format dump."""
+    res = {}
+    c = corrx.Correlator(n, fc, tc)
+    lane_bytes = (fc // 128) * 4 * tc * 256
+    lanes = [x[k * lane_bytes:(k + 1) * lane_bytes] for k in range(8 * (n // 64))]
+    out = torch.empty_like(x)
+    for name, order in (("ingest_natural", corrx.CORRX_ORDER_NATURAL), ("ingest_packet", corrx.CORRX_ORDER_PACKET)):
+        ms = time_ms(torch, lambda: corrx.corr_pfb_ingest(c.h, lanes, order, out), 10)
+        nbytes = 2 * x.numel()
+        res[name] = {"ms": round(ms, 3), "gbs": round(nbytes / ms / 1e6, 1),
+                     "hbm_frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 3), "bytes": nbytes}
+        log(f"{name}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
+    del out
+    acc = c.new_acc(dev)
+    c.zero(acc)
+    c.xmac(x, acc)
+    acc2 = torch.empty_like(acc)
+    ms = time_ms(torch, lambda: corrx.corr_pfb_remap(c.h, acc, acc2), 10)
+    nbytes = 2 * acc.numel() * 4
+    res["remap"] = {"ms": round(ms, 3), "gbs": round(nbytes / ms / 1e6, 1),
+                    "hbm_frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 3), "bytes": nbytes}
+    log(f"remap: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
+    del acc2
+    for f_avg in (1, 2):
+        cnt = corrx.corr_dump_count(c.h, corrx.CORRX_TRI_STATION_POL) // f_avg
+        dst = torch.empty(cnt, dtype=torch.float32, device=dev)
+        ms = time_ms(torch, lambda: corrx.corr_dump_avg(c.h, acc, corrx.CORRX_TRI_STATION_POL, corrx.CORRX_F32,
+                                                          f_avg, 2 if f_avg == 2 else 1, dst), 10)
+        nbytes = acc.numel() * 4 + cnt * 4
+        res[f"dump_station_pol_f32_favg{f_avg}"] = {"ms": round(ms, 3), "gbs": round(nbytes / ms / 1e6, 1),
+                                                    "hbm_frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 3),
+                                                    "bytes": nbytes}
+        log(f"dump f_avg {f_avg}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
+        del dst
+    del acc
+    c.close()
+    return res
 
 
 STREAM = [("obs256x3072", 256, 3072), ("obs256x768", 256, 768), ("obs512x384", 512, 384), ("obs128x3072", 128, 3072)]

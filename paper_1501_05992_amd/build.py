@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcorrx.so")
-SOURCES = ["api.hip", "batch.hip", "xengine_mfma.hip", "xengine_fp8.hip", "xengine_plain.hip", "dump.hip"]
+SOURCES = ["api.hip", "batch.hip", "xengine_mfma.hip", "xengine_plain.hip", "dump.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-fp32 instructions are disabled for every device compile.
@@ -27,9 +27,11 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 
 def build(verbose: bool = False, save_temps_dir: str | None = None) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *DEVICE_FLAGS, "-shared", "-I", os.path.join(ROOT, "include"), "-o", tmp, *srcs]
+    # --no-undefined: a missing definition fails the build instead of the load.
+    cmd = [HIPCC, *DEVICE_FLAGS, "-shared", "-Wl,--no-undefined", "-I", os.path.join(ROOT, "include"), "-o", tmp,
+           *srcs]
     if save_temps_dir:
         os.makedirs(save_temps_dir, exist_ok=True)
         cmd.insert(1, f"-save-temps={save_temps_dir}")

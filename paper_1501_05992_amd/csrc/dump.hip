@@ -57,8 +57,13 @@ __global__ void dump_tri(const int2* acc, T* dst, int64_t nb, int fa, float scal
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
     const int64_t g = k / nb, b = k % nb;
     const int2 v = chan_sum(acc, nb, g, fa, b);
-    dst[2 * k] = conv<T>(v.x, scale);
-    dst[2 * k + 1] = conv<T>(v.y, scale);
+    if (((reinterpret_cast<uintptr_t>(dst)) & 7) == 0) {
+      using V2 = typename std::conditional<std::is_same<T, float>::value, float2, int2>::type;
+      reinterpret_cast<V2*>(dst)[k] = V2{conv<T>(v.x, scale), conv<T>(v.y, scale)};
+    } else {
+      dst[2 * k] = conv<T>(v.x, scale);
+      dst[2 * k + 1] = conv<T>(v.y, scale);
+    }
   }
 }
 
@@ -67,7 +72,9 @@ __global__ void dump_tri(const int2* acc, T* dst, int64_t nb, int fa, float scal
 // polarisation products (p1, p2) = (0,0), (0,1), (1,0), (1,1), complex; the
 // inputs are i = 2 s1 + p1, j = 2 s2 + p2, and (s, s, 0, 1) is the conjugate
 // of the stored (2s+1, 2s) element.
-template <typename T>
+// VEC: dst is 16-byte aligned and each thread's 32 bytes go out as two
+// 16-byte stores.
+template <typename T, bool VEC>
 __global__ void dump_station_pol(const int2* acc, T* dst, int n_inputs, int64_t n_station_bl, int fa, float scale,
                                  int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -76,7 +83,7 @@ __global__ void dump_station_pol(const int2* acc, T* dst, int n_inputs, int64_t 
     const int64_t g = o / n_station_bl, bs = o % n_station_bl;
     int s1, s2;
     tri_decode(bs, s1, s2);
-    T* out = dst + 8 * o;
+    T val[8];
 #pragma unroll
     for (int p1 = 0; p1 < 2; ++p1)
 #pragma unroll
@@ -89,9 +96,18 @@ __global__ void dump_station_pol(const int2* acc, T* dst, int n_inputs, int64_t 
           v = chan_sum(acc, nb, g, fa, tri_index(j, i));
           v.y = -v.y;
         }
-        out[4 * p1 + 2 * p2] = conv<T>(v.x, scale);
-        out[4 * p1 + 2 * p2 + 1] = conv<T>(v.y, scale);
+        val[4 * p1 + 2 * p2] = conv<T>(v.x, scale);
+        val[4 * p1 + 2 * p2 + 1] = conv<T>(v.y, scale);
       }
+    T* out = dst + 8 * o;
+    if constexpr (VEC) {
+      using V4 = typename std::conditional<std::is_same<T, float>::value, float4, int4>::type;
+      reinterpret_cast<V4*>(out)[0] = V4{val[0], val[1], val[2], val[3]};
+      reinterpret_cast<V4*>(out)[1] = V4{val[4], val[5], val[6], val[7]};
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) out[q] = val[q];
+    }
   }
 }
 
@@ -109,13 +125,20 @@ int launch_dump(const int* acc, int n_inputs, int n_chan, int order, int dtype, 
       hipLaunchKernelGGL(dump_tri<int>, g, b, 0, s, a2, reinterpret_cast<int*>(dst), nb, f_avg, scale, n);
     else
       hipLaunchKernelGGL(dump_tri<float>, g, b, 0, s, a2, reinterpret_cast<float*>(dst), nb, f_avg, scale, n);
+  } else if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+    if (dtype == CORRX_I32)
+      hipLaunchKernelGGL((dump_station_pol<int, true>), g, b, 0, s, a2, reinterpret_cast<int*>(dst), n_inputs, nsb,
+                         f_avg, scale, n);
+    else
+      hipLaunchKernelGGL((dump_station_pol<float, true>), g, b, 0, s, a2, reinterpret_cast<float*>(dst), n_inputs,
+                         nsb, f_avg, scale, n);
   } else {
     if (dtype == CORRX_I32)
-      hipLaunchKernelGGL(dump_station_pol<int>, g, b, 0, s, a2, reinterpret_cast<int*>(dst), n_inputs, nsb, f_avg,
-                         scale, n);
+      hipLaunchKernelGGL((dump_station_pol<int, false>), g, b, 0, s, a2, reinterpret_cast<int*>(dst), n_inputs,
+                         nsb, f_avg, scale, n);
     else
-      hipLaunchKernelGGL(dump_station_pol<float>, g, b, 0, s, a2, reinterpret_cast<float*>(dst), n_inputs, nsb,
-                         f_avg, scale, n);
+      hipLaunchKernelGGL((dump_station_pol<float, false>), g, b, 0, s, a2, reinterpret_cast<float*>(dst),
+                         n_inputs, nsb, f_avg, scale, n);
   }
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
@@ -133,9 +156,13 @@ __device__ inline int pfb_pos_of_input(int a) { return 4 * (a & 15) + (a >> 4); 
 // columns 64b ..  Packet order copies the 16 bytes; natural order transposes
 // them as a 4 x 4 byte block, since positions 16u .. 16u+15 hold inputs
 // 16r + 4u + q (r = position % 4, q = 0..3), i.e. byte r of each of the four
-// dwords goes to dword 4r + u of the row segment.
-__global__ void pfb_ingest(PfbLanes lanes, uint8_t* out, int n_pfb, int n_coarse, int n_time, int natural,
-                           int64_t n_waves) {
+// dwords goes to dword 4r + u of the row segment; the dwords are regrouped
+// through the wave's own 1 KB of LDS so that every lane stores 16 contiguous
+// bytes.
+__global__ __launch_bounds__(256) void pfb_ingest(PfbLanes lanes, uint8_t* out, int n_pfb, int n_coarse,
+                                                  int n_time, int natural, int64_t n_waves) {
+  __shared__ __attribute__((aligned(16))) uint32_t stage[4][256];  // per wave: 4 rows x 64 dwords
+  uint32_t* ws = stage[threadIdx.x >> 6];
   const int lane = threadIdx.x & 63;
   const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
   const int b = lane >> 4, j = lane & 15, f2 = j >> 2, u = j & 3;
@@ -158,10 +185,20 @@ __global__ void pfb_ingest(PfbLanes lanes, uint8_t* out, int n_pfb, int n_coarse
     } else {
       uint32_t e0, e1, e2, e3;
       transpose4x4(v.x, v.y, v.z, v.w, e0, e1, e2, e3);
-      *reinterpret_cast<uint32_t*>(row + 4 * u) = e0;
-      *reinterpret_cast<uint32_t*>(row + 16 + 4 * u) = e1;
-      *reinterpret_cast<uint32_t*>(row + 32 + 4 * u) = e2;
-      *reinterpret_cast<uint32_t*>(row + 48 + 4 * u) = e3;
+      uint32_t* seg = ws + 64 * f2 + 16 * b;  // row f2, PFB b: 16 dwords
+      seg[u] = e0;
+      seg[4 + u] = e1;
+      seg[8 + u] = e2;
+      seg[12 + u] = e3;
+      // The LDS unit runs one wave's operations in order; keep the compiler
+      // from moving the reads above the writes.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      *reinterpret_cast<uint4*>(row + 16 * u) = reinterpret_cast<const uint4*>(seg)[u];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
@@ -176,33 +213,39 @@ int launch_pfb_ingest(const PfbLanes& lanes, uint8_t* out, int n_pfb, int n_coar
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
-// Product remap, packet order -> natural order, one thread per output element:
-// natural inputs i >= j sit at packet indices P(i), P(j); the product is
-// V_pkt[P(i)][P(j)] when P(i) >= P(j), else the conjugate of V_pkt[P(j)][P(i)].
-__global__ void pfb_remap(const int2* src, int2* dst, int n_inputs, int64_t nb, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
-    const int64_t f = k / nb, b = k % nb;
-    int i, j;
-    tri_decode(b, i, j);
-    const int pi = (i & ~63) + pfb_pos_of_input(i & 63), pj = (j & ~63) + pfb_pos_of_input(j & 63);
-    int2 v;
-    if (pi >= pj) {
-      v = src[f * nb + tri_index(pi, pj)];
-    } else {
-      v = src[f * nb + tri_index(pj, pi)];
-      v.y = -v.y;
+// Product remap, packet order -> natural order: natural inputs i >= j sit at
+// packet indices P(i), P(j); the product is V_pkt[P(i)][P(j)] when
+// P(i) >= P(j), else the conjugate of V_pkt[P(j)][P(i)].  One thread per
+// baseline decodes (i, j) once and moves it for kRemapChans channels
+// (blockIdx.y picks the channel group).
+constexpr int kRemapChans = 8;
+
+__global__ void pfb_remap(const int2* src, int2* dst, int n_chan, int64_t nb) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  int i, j;
+  tri_decode(b, i, j);
+  const int pi = (i & ~63) + pfb_pos_of_input(i & 63), pj = (j & ~63) + pfb_pos_of_input(j & 63);
+  const bool direct = pi >= pj;
+  const int64_t from = direct ? tri_index(pi, pj) : tri_index(pj, pi);
+  for (int f0 = blockIdx.y * kRemapChans; f0 < n_chan; f0 += gridDim.y * kRemapChans) {
+    const int f1 = min(n_chan, f0 + kRemapChans);
+    for (int f = f0; f < f1; ++f) {
+      int2 v = src[(int64_t)f * nb + from];
+      if (!direct) v.y = -v.y;
+      dst[(int64_t)f * nb + b] = v;
     }
-    dst[k] = v;
   }
 }
 
 int launch_pfb_remap(const int* src, int* dst, int n_inputs, int n_chan, hipStream_t s) {
   const int64_t nb = tri_index(n_inputs, 0);
-  const int64_t n = (int64_t)n_chan * nb;
-  const int grid = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
-  hipLaunchKernelGGL(pfb_remap, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, reinterpret_cast<const int2*>(src),
-                     reinterpret_cast<int2*>(dst), n_inputs, nb, n);
+  const int64_t gx = (nb + 255) / 256;
+  int64_t gy = (n_chan + kRemapChans - 1) / kRemapChans;
+  if (gy > 65535) gy = 65535;
+  if (gx > 0x7FFFFFFF) return CORRX_EINVAL;
+  hipLaunchKernelGGL(pfb_remap, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s,
+                     reinterpret_cast<const int2*>(src), reinterpret_cast<int2*>(dst), n_chan, nb);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
