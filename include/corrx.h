@@ -43,6 +43,7 @@ extern "C" {
 
 typedef struct corrx_ctx *corrx_t;
 typedef struct corrx_batch *corrx_batch_t;
+typedef struct corrx_fpfb *corrx_fpfb_t;
 
 /* Status codes. */
 enum {
@@ -193,6 +194,48 @@ int corr_pfb_ingest(corrx_t h, const void *const *lanes, int order, void *in, vo
  * aligned, not overlapping); n_inputs must be a multiple of 64.
  */
 int corr_pfb_remap(corrx_t h, const void *acc_pkt, void *acc_nat, void *stream);
+
+/* ---- Fine polyphase filterbank, the F-engine stage (Sec. 3.2.1) ------- */
+
+/*
+ * 12-tap, 128-point critically sampled polyphase filterbank turning complex
+ * coarse-channel samples into the packed 4+4-bit samples of 128 fine channels
+ * (the input of corr_xmac).  Fixed point, so the output is an exact function
+ * of the input (the paper gives no filter or quantiser; these are ours):
+ *   v[k][p] = sum_{j<12} h[128 j + p] x[128 (k + j) + p]      (complex, int32)
+ *   v8 = clip(round_shift(v, s1), -127, 127)
+ *   Y[k][q] = sum_{p<128} v8[k][p] W[p q mod 128]             (complex, int32)
+ *   sample = clip(round_shift(Y, s2), -7, 7) at fine channel (q + 64) mod 128
+ * with round_shift(v, s) = floor((v + 2^(s-1)) / 2^s), h = rint(32767 w sinc /
+ * peak) (w the 1536-point Hann window, sinc centred at 767.5 with period 128),
+ * W[n] = rint(127 exp(-2 pi i n / 128)).
+ * corr_fpfb_create: n_inputs a multiple of 64 (else CORRX_EUNSUPPORTED),
+ * n_coarse coarse channels, n_frames output samples per fine channel; builds
+ * the tables on the host and copies them to the current device (owned by the
+ * handle, 67 KB).
+ */
+int corr_fpfb_create(int n_inputs, int n_coarse, int n_frames, corrx_fpfb_t *out);
+int corr_fpfb_destroy(corrx_fpfb_t h);
+
+/* Bytes of the device workspace corr_fpfb needs: n_coarse * n_inputs * n_frames * 256. */
+size_t corr_fpfb_workspace_bytes(corrx_fpfb_t h);
+
+/* Copy the handle's tables to HOST memory (either pointer may be NULL):
+ * taps[1536]; twiddle_matrix[256 * 256] = row n, column k of the real GEMM
+ * operand [[Wr, Wi], [-Wi, Wr]] transposed (k < 128: real part of input p = k,
+ * else imaginary part of p = k - 128; n < 128: real part of output q = n, else
+ * imaginary part of q = n - 128). */
+int corr_fpfb_tables(corrx_fpfb_t h, int16_t *taps, int8_t *twiddle_matrix);
+
+/*
+ * in: device, complex int8 pairs (re, im) laid out [c][i][n], n = 0 ..
+ * 128 (n_frames + 11) - 1 (each frame needs the 11 before it), 2-byte
+ * aligned.  work: device workspace (corr_fpfb_workspace_bytes, 16-byte
+ * aligned).  out: device, TFI packed samples n_frames * (128 n_coarse) *
+ * n_inputs bytes, 16-byte aligned: byte (k, 128 c + f, i).  Two launches on
+ * `stream` (filter, then DFT and requantisation).  0 <= s1, s2 <= 30.
+ */
+int corr_fpfb(corrx_fpfb_t h, const void *in, int s1, int s2, void *work, void *out, void *stream);
 
 /* Samples accumulated since the last corr_zero (host-side count). */
 int64_t corr_samples(corrx_t h);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcorrx.so")
-SOURCES = ["api.hip", "batch.hip", "xengine_mfma.hip", "xengine_plain.hip", "dump.hip"]
+SOURCES = ["api.hip", "batch.hip", "xengine_mfma.hip", "xengine_plain.hip", "dump.hip", "fpfb.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-fp32 instructions are disabled for every device compile.

@@ -12,6 +12,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 import torch  # noqa: F401  (loads the HIP runtime first; see module docstring)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,7 +49,8 @@ ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
 # Exported symbols, in header order.
 SYMBOLS = ("corr_abi_version", "corr_strerror", "corr_create", "corr_destroy", "corr_set_engine",
            "corr_get_engine", "corr_acc_bytes", "corr_dump_count", "corr_zero", "corr_xmac",
-           "corr_dump", "corr_dump_avg", "corr_pfb_ingest", "corr_pfb_remap", "corr_samples",
+           "corr_dump", "corr_dump_avg", "corr_pfb_ingest", "corr_pfb_remap", "corr_fpfb_create",
+           "corr_fpfb_destroy", "corr_fpfb_workspace_bytes", "corr_fpfb_tables", "corr_fpfb", "corr_samples",
            "corr_beam", "corr_batch_create", "corr_batch_destroy",
            "corr_batch_items", "corr_batch_plan", "corr_batch_zero", "corr_batch_xmac")
 
@@ -90,6 +93,11 @@ def lib() -> ctypes.CDLL:
             "corr_dump_avg": ([vp, vp, i, i, i, i, vp, vp], i),
             "corr_pfb_ingest": ([vp, ctypes.POINTER(vp), i, vp, vp], i),
             "corr_pfb_remap": ([vp, vp, vp, vp], i),
+            "corr_fpfb_create": ([i, i, i, ctypes.POINTER(vp)], i),
+            "corr_fpfb_destroy": ([vp], i),
+            "corr_fpfb_workspace_bytes": ([vp], sz),
+            "corr_fpfb_tables": ([vp, ctypes.POINTER(ctypes.c_int16), ctypes.POINTER(ctypes.c_int8)], i),
+            "corr_fpfb": ([vp, vp, i, i, vp, vp, vp], i),
             "corr_samples": ([vp], i64),
             "corr_beam": ([vp, vp, vp, vp], i),
             "corr_batch_create": ([ctypes.POINTER(corrx_desc), i, i, ctypes.POINTER(ctypes.c_int),
@@ -193,6 +201,32 @@ def corr_pfb_ingest(h: int, lanes, order: int, inp, stream=None) -> None:
 
 def corr_pfb_remap(h: int, acc_pkt, acc_nat, stream=None) -> None:
     _check(lib().corr_pfb_remap(h, _ptr(acc_pkt), _ptr(acc_nat), _stream(stream)), "corr_pfb_remap")
+
+
+def corr_fpfb_create(n_inputs: int, n_coarse: int, n_frames: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().corr_fpfb_create(n_inputs, n_coarse, n_frames, ctypes.byref(h)), "corr_fpfb_create")
+    return h.value
+
+
+def corr_fpfb_destroy(h: int) -> None:
+    _check(lib().corr_fpfb_destroy(h), "corr_fpfb_destroy")
+
+
+def corr_fpfb_workspace_bytes(h: int) -> int:
+    return int(lib().corr_fpfb_workspace_bytes(h))
+
+
+def corr_fpfb_tables(h: int):
+    taps = np.zeros(1536, dtype=np.int16)
+    wmat = np.zeros(256 * 256, dtype=np.int8)
+    _check(lib().corr_fpfb_tables(h, taps.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)),
+                                  wmat.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), "corr_fpfb_tables")
+    return taps, wmat.reshape(256, 256)
+
+
+def corr_fpfb(h: int, inp, s1: int, s2: int, work, out, stream=None) -> None:
+    _check(lib().corr_fpfb(h, _ptr(inp), s1, s2, _ptr(work), _ptr(out), _stream(stream)), "corr_fpfb")
 
 
 def corr_beam(h: int, inp, out, stream=None) -> None:
@@ -317,6 +351,44 @@ class Correlator:
     @property
     def samples(self) -> int:
         return corr_samples(self.h)
+
+
+class FineFilterbank:
+    """The F-engine stage: complex int8 coarse-channel samples [c][i][n] to the
+    packed 4+4-bit TFI input of the X-engine (corr_fpfb)."""
+
+    def __init__(self, n_inputs: int, n_coarse: int, n_frames: int):
+        self.n_inputs, self.n_coarse, self.n_frames = n_inputs, n_coarse, n_frames
+        self.h = corr_fpfb_create(n_inputs, n_coarse, n_frames)
+        self._work = None
+
+    def close(self) -> None:
+        if self.h:
+            corr_fpfb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_samples(self) -> int:
+        """Complex input samples per (coarse channel, input)."""
+        return 128 * (self.n_frames + 11)
+
+    def tables(self):
+        return corr_fpfb_tables(self.h)
+
+    def run(self, inp, s1: int, s2: int, out=None, stream=None):
+        dev = inp.device
+        if self._work is None or self._work.device != dev:
+            self._work = torch.empty(corr_fpfb_workspace_bytes(self.h), dtype=torch.uint8, device=dev)
+        if out is None:
+            out = torch.empty(self.n_frames * 128 * self.n_coarse * self.n_inputs, dtype=torch.uint8, device=dev)
+        corr_fpfb(self.h, inp, s1, s2, self._work, out, stream)
+        return out
 
 
 class Batch:

@@ -143,6 +143,19 @@ def lane_payloads(seed: int, n_pfb: int, n_coarse: int, n_time: int) -> list[np.
     return out
 
 
+def coarse_samples(seed: int, n_coarse: int, n_inputs: int, n_samples: int, rms: float = 16.0) -> np.ndarray:
+    """Complex int8 coarse-channel voltages laid out [c][i][n][re, im]:
+    seeded Gaussian noise of the given RMS per part, rounded and clipped to
+    [-127, 127]; one Philox stream per (coarse channel, input)."""
+    out = np.empty((n_coarse, n_inputs, n_samples, 2), dtype=np.int8)
+    for c in range(n_coarse):
+        for i in range(n_inputs):
+            rng = _rng(seed, 2000 + c, i)
+            z = rng.standard_normal((n_samples, 2), dtype=np.float32) * np.float32(rms)
+            out[c, i] = np.clip(np.rint(z), -127, 127).astype(np.int8)
+    return out.reshape(-1)
+
+
 def tone_input(gains_re: np.ndarray, gains_im: np.ndarray, n_chan: int, n_time: int,
                layout: int = LAYOUT_TFI) -> np.ndarray:
     """Single injected tone x_i(t) = g_i * j**t, identical in every channel.
