@@ -261,6 +261,7 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
     del x2
     out["uneven_batch"] = uneven_batch(corrx, model, synth, torch, dev, oracle)
     out["pfb_and_output"] = pfb_and_output(corrx, torch, dev, x, n, fc, tc)
+    out["fine_pfb"] = fine_pfb(corrx, torch, dev, n, fc // 128)
     out["streaming"] = streaming(synth, torch)
     return out
 
@@ -276,6 +277,29 @@ def time_ms(torch, fn, reps):
         b.record(s)
     torch.cuda.synchronize()
     return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def fine_pfb(corrx, torch, dev, n, n_coarse, n_frames=2000, s1=13, s2=15):
+    """F-engine at the full band's shape: n inputs x n_coarse coarse channels,
+    2000 output frames (0.2 s of data), complex int8 input of RMS 16 drawn on
+    the device."""
+    fb = corrx.FineFilterbank(n, n_coarse, n_frames)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1501)
+    x = torch.randn(n_coarse * n * fb.n_samples * 2, device=dev, generator=g).mul_(16).round_().clamp_(-127, 127)
+    x = x.to(torch.int8).view(torch.uint8)
+    out = torch.empty(n_frames * 128 * n_coarse * n, dtype=torch.uint8, device=dev)
+    ms = time_ms(torch, lambda: fb.run(x, s1, s2, out), 5)
+    data_s = n_frames / 1e4
+    in_b, ws_b, out_b = x.numel(), corrx.corr_fpfb_workspace_bytes(fb.h), out.numel()
+    dft_ops = 2.0 * 256 * 256 * n_frames * n * n_coarse
+    res = {"shape": [n, n_coarse, n_frames], "ms": round(ms, 3), "xrt": round(data_s / (ms * 1e-3), 1),
+           "bytes": in_b + 2 * ws_b + out_b, "gbs": round((in_b + 2 * ws_b + out_b) / ms / 1e6, 1),
+           "dft_mfma_tops": round(dft_ops / ms / 1e9, 1)}
+    log(f"fine PFB: {ms:.3f} ms for {data_s} s of data ({res['xrt']}x real time)")
+    del x, out
+    fb.close()
+    return res
 
 
 def pfb_and_output(corrx, torch, dev, x, n, fc, tc):
