@@ -88,7 +88,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the X-engine shards by "
+        print(f"bench.py: this benchmark measures one GPU only (asked for {args.gpus}); the X-engine shards by "
               "channel with no exchange, so N GPUs would each run this same per-GPU workload.", file=sys.stderr)
         sys.exit(2)
 

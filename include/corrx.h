@@ -51,7 +51,7 @@ enum {
     CORRX_EINVAL = -1,       /* bad argument: null pointer, size, enum value */
     CORRX_ENOMEM = -2,       /* host or device allocation failed */
     CORRX_EDEVICE = -3,      /* no usable gfx950 device, or a HIP call / launch failed */
-    CORRX_EUNSUPPORTED = -4, /* valid request this build cannot serve */
+    CORRX_EUNSUPPORTED = -4, /* valid request this library does not serve */
     CORRX_EOVERFLOW = -5     /* the int32 accumulator could overflow: zero it first */
 };
 
