@@ -168,3 +168,45 @@ def test_pfb_shape_checks(cx):
         c.pfb_remap(acc)
     assert e.value.status == cx.CORRX_EUNSUPPORTED
     c.close()
+
+
+def test_ingest_single_time_step(cx):
+    import torch
+
+    lanes = synth.lane_payloads(9, 2, 1, 1)
+    c = cx.Correlator(128, 128, 1)
+    for natural in (False, True):
+        got = c.pfb_ingest(_lanes_dev(lanes), cx.CORRX_ORDER_NATURAL if natural else cx.CORRX_ORDER_PACKET)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), opfb.ingest(lanes, 2, 1, 1, natural))
+    c.close()
+
+
+def test_remap_ragged_channel_count(cx):
+    # 13 channels: the remap handles channels in groups of 8
+    import torch
+
+    N, F = 128, 13
+    rng = np.random.default_rng(13)
+    src = rng.integers(-1000, 1000, size=(F, N * (N + 1) // 2, 2), dtype=np.int64).astype(np.int32)
+    c = cx.Correlator(N, F, 10)
+    got = c.pfb_remap(torch.from_numpy(src).to(_dev()))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().astype(np.int64), opfb.remap(src.astype(np.int64), N))
+    c.close()
+
+
+def test_dump_avg_rejects_odd_station_pol_and_overlap(cx):
+    import torch
+
+    c = cx.Correlator(15, 4, 10)
+    acc = c.new_acc(_dev())
+    c.zero(acc)
+    dst = torch.empty(4 * 120 * 2, dtype=torch.float32, device=_dev())
+    with pytest.raises(cx.CorrxError) as e:
+        cx.corr_dump_avg(c.h, acc, cx.CORRX_TRI_STATION_POL, cx.CORRX_F32, 2, 1, dst)
+    assert e.value.status == cx.CORRX_EINVAL
+    with pytest.raises(cx.CorrxError) as e:  # destination overlapping the accumulator
+        cx.corr_dump_avg(c.h, acc, cx.CORRX_TRI_INPUT, cx.CORRX_I32, 2, 1, acc)
+    assert e.value.status == cx.CORRX_EINVAL
+    c.close()
