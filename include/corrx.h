@@ -229,7 +229,7 @@ int corr_fpfb_tables(corrx_fpfb_t h, int16_t *taps, int8_t *twiddle_matrix);
 
 /*
  * in: device, complex int8 pairs (re, im) laid out [c][i][n], n = 0 ..
- * 128 (n_frames + 11) - 1 (each frame needs the 11 before it), 2-byte
+ * 128 (n_frames + 11) - 1 (each frame needs the 11 before it), 4-byte
  * aligned.  work: device workspace (corr_fpfb_workspace_bytes, 16-byte
  * aligned).  out: device, TFI packed samples n_frames * (128 n_coarse) *
  * n_inputs bytes, 16-byte aligned: byte (k, 128 c + f, i).  Two launches on
