@@ -32,10 +32,7 @@ namespace {
 
 constexpr int kM = 128, kTaps = 12, kL = kM * kTaps;
 constexpr int kFirFrames = 32;  // frames per FIR thread
-constexpr int kDftInputs = 64;  // inputs per DFT tile
-constexpr int kDftFrames = 4;   // frames per DFT tile: 256 GEMM rows
-
-__device__ inline int round_shift(int v, int s) { return s > 0 ? (v + (1 << (s - 1))) >> s : v; }
+constexpr int kDftRows = 256;  // GEMM rows per DFT tile: NI inputs x 256 / NI frames
 
 typedef short v2s __attribute__((ext_vector_type(2)));
 
@@ -84,7 +81,7 @@ __global__ __launch_bounds__(64) void fpfb_fir(const uint32_t* in, int8_t* work,
     pi0[m] = pair16<0>(raw[m], raw[m + 1]);
     pi1[m] = pair16<1>(raw[m], raw[m + 1]);
   }
-  const int bias = s1 > 0 ? 1 << (s1 - 1) : 0;  // round_shift's rounding term
+  const int bias = s1 > 0 ? 1 << (s1 - 1) : 0;  // the rounding term of round_shift
   int8_t* out = work + ((int64_t)ci * n_frames + k0) * 256 + p;
 #pragma unroll
   for (int k = 0; k < kFirFrames; ++k) {
@@ -114,8 +111,12 @@ __device__ inline int swz16(int row) { return (row ^ (row >> 2)) & 15; }
 // the 16-byte reads of the write phase.
 __device__ inline int swzc(int col) { return ((col & 3) << 2) | ((col >> 2) & 3); }
 
+// NI inputs per tile (64, or 128 when the array allows it, so that each
+// output row segment is a whole 128-byte line).
+template <int NI>
 __global__ __launch_bounds__(512, 1) void fpfb_dft(const int8_t* work, const int8_t* wmat, uint8_t* out,
                                                    int n_inputs, int n_coarse, int n_frames, int s2) {
+  constexpr int NF = kDftRows / NI;  // frames per tile
   // lds: the A tile (256 rows of 256 bytes), reused for the transposed codes;
   // ldb: the twiddle matrix (the B operand, wmat[n][k], 256 x 256 int8) for
   // the whole launch.  Both are stored as 16 granules of 16 bytes per row,
@@ -125,8 +126,9 @@ __global__ __launch_bounds__(512, 1) void fpfb_dft(const int8_t* work, const int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 2, wc = wave & 3;
   const int half = lane >> 5;
-  const int iblocks = n_inputs / kDftInputs;
-  const int kblocks = (n_frames + kDftFrames - 1) / kDftFrames;
+  const int iblocks = n_inputs / NI;
+  const int kblocks = (n_frames + NF - 1) / NF;
+  const int bias = s2 > 0 ? 1 << (s2 - 1) : 0;
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
     const int idx = tid + 512 * g, row = idx >> 4, gr = idx & 15;
@@ -134,11 +136,11 @@ __global__ __launch_bounds__(512, 1) void fpfb_dft(const int8_t* work, const int
         *reinterpret_cast<const v4i*>(wmat + row * 256 + 16 * gr);
   }
 
-  // Tile t: frames 4 (t % kblocks) .., inputs 64 ((t / kblocks) % iblocks) ..,
-  // coarse channel t / (kblocks iblocks).  Each thread loads 8 granules of 16
-  // bytes of the A tile: row (k_l, i_l) = work[c][i0 + i_l][k0 + k_l][0..255]
-  // (granule g belongs to frame k_l = g / 2); frames past the end are loaded
-  // clamped and zeroed when staged.  The next tile's granules are loaded into
+  // Tile t: frames NF (t % kblocks) .., inputs NI ((t / kblocks) % iblocks)
+  // .., coarse channel t / (kblocks iblocks).  Each thread loads 8 granules of
+  // 16 bytes of the A tile: row k_l NI + i_l = work[c][i0 + i_l][k0 + k_l][..]
+  // (granule g belongs to frame k_l = g / (NI / 32)); frames past the end are
+  // loaded clamped and zeroed when staged.  The next tile's granules are loaded into
   // registers while the current one is multiplied.
   const int tiles = n_coarse * iblocks * kblocks;  // < 2^31, checked by the host
   auto load_tile = [&](int t, v4i* v) {
@@ -148,10 +150,10 @@ __global__ __launch_bounds__(512, 1) void fpfb_dft(const int8_t* work, const int
     for (int g = 0; g < 8; ++g) {
       const int idx = tid + 512 * g;  // 4096 granules
       const int row = idx >> 4, gr = idx & 15;
-      const int kl = row >> 6, il = row & 63;
-      const int k = kb * kDftFrames + kl;
+      const int kl = row / NI, il = row % NI;
+      const int k = kb * NF + kl;
       v[g] = *reinterpret_cast<const v4i*>(
-          work + (((int64_t)c * n_inputs + ib * kDftInputs + il) * n_frames + min(k, n_frames - 1)) * 256 + 16 * gr);
+          work + (((int64_t)c * n_inputs + ib * NI + il) * n_frames + min(k, n_frames - 1)) * 256 + 16 * gr);
     }
   };
   v4i next[8];
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(512, 1) void fpfb_dft(const int8_t* work, const int
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int kb = tile % kblocks, rest = tile / kblocks;
     const int ib = rest % iblocks, c = rest / iblocks;
-    const int i0 = ib * kDftInputs, k0 = kb * kDftFrames;
+    const int i0 = ib * NI, k0 = kb * NF;
     // Stage the A tile.
     __syncthreads();
 #pragma unroll
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(512, 1) void fpfb_dft(const int8_t* work, const int
       const int idx = tid + 512 * g;
       const int row = idx >> 4, gr = idx & 15;
       *reinterpret_cast<v4i*>(lds + row * 256 + ((gr ^ swz16(row)) << 4)) =
-          k0 + (g >> 1) < n_frames ? next[g] : v4i{0, 0, 0, 0};
+          k0 + g / (NI / 32) < n_frames ? next[g] : v4i{0, 0, 0, 0};
     }
     __syncthreads();
     if (tile + (int)gridDim.x < tiles) load_tile(tile + gridDim.x, next);
@@ -175,7 +177,9 @@ __global__ __launch_bounds__(512, 1) void fpfb_dft(const int8_t* work, const int
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int z = 0; z < 2; ++z) acc[x][z] = v16i{0};
+      for (int z = 0; z < 2; ++z)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[x][z][r] = bias;  // the rounding term of round_shift
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       v4i a[4], b[2];
@@ -205,27 +209,29 @@ __global__ __launch_bounds__(512, 1) void fpfb_dft(const int8_t* work, const int
         const int col = 64 * wc + 32 * z + (lane & 31);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          uint32_t word = 0;
+          int q[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int q = min(7, max(-7, round_shift(acc[x][z][4 * m + r], s2)));
-            word |= (uint32_t)(q & 0xFF) << (8 * r);
-          }
+          for (int r = 0; r < 4; ++r) q[r] = min(7, max(-7, acc[x][z][4 * m + r] >> s2));
+          // low bytes of q0..q3 into one word (v_perm_b32: 0..3 select src1's
+          // bytes, 4..7 src0's, 12 gives zero)
+          const uint32_t word = __builtin_amdgcn_perm(q[1], q[0], 0x0C0C0400u) |
+                                __builtin_amdgcn_perm(q[3], q[2], 0x04000C0Cu);
           const int row = 128 * wr + 32 * x + 8 * m + 4 * half;
           *reinterpret_cast<uint32_t*>(lds + col * 256 + (((row >> 4) ^ swzc(col)) << 4) + (row & 15)) = word;
         }
       }
     __syncthreads();
-    // Pack and write: thread -> (k_l, q, 16-input segment): bytes
-    // (re << 4) | (im & 15) for inputs i0 + 16 s .. +15 of row (k0 + k_l,
-    // channel 128 c + (q + 64) % 128).
+    // Pack and write: thread -> (q, segment s mod 4), four (k_l, s) in turn:
+    // bytes (re << 4) | (im & 15) for inputs i0 + 16 s .. +15 of row
+    // (k0 + k_l, channel 128 c + (q + 64) % 128).
     {
-      const int s = tid & 3, q = (tid >> 2) & 127;
+      const int s4 = tid & 3, q = tid >> 2;
       const int n_chan = 128 * n_coarse;
 #pragma unroll
-      for (int kl = 0; kl < kDftFrames; ++kl) {
+      for (int it = 0; it < 4; ++it) {
+        const int kl = it / (NI / 64), s = s4 + 4 * (it % (NI / 64));
         if (k0 + kl >= n_frames) break;
-        const int g = ((4 * kl + s) ^ swzc(q)) << 4;  // swzc(128 + q) == swzc(q)
+        const int g = ((kl * (NI / 16) + s) ^ swzc(q)) << 4;  // swzc(128 + q) == swzc(q)
         const uint4 re = *reinterpret_cast<const uint4*>(lds + q * 256 + g);
         const uint4 im = *reinterpret_cast<const uint4*>(lds + (128 + q) * 256 + g);
         uint4 o;
@@ -295,7 +301,7 @@ int corr_fpfb_create(int n_inputs, int n_coarse, int n_frames, corrx_fpfb_t* out
   if (!out) return CORRX_EINVAL;
   *out = nullptr;
   if (n_inputs < 1 || n_coarse < 1 || n_frames < 1) return CORRX_EINVAL;
-  if (n_inputs % kDftInputs) return CORRX_EUNSUPPORTED;
+  if (n_inputs % 64) return CORRX_EUNSUPPORTED;
   if ((double)n_coarse * n_inputs * (n_frames + kTaps - 1) * kM * 2 >= 1099511627776.0) return CORRX_EINVAL;
   int dev = 0;
   hipDeviceProp_t prop;
@@ -362,14 +368,19 @@ int corr_fpfb(corrx_fpfb_t h, const void* in, int s1, int s2, void* work, void* 
   hipLaunchKernelGGL(fpfb_fir, dim3((unsigned)fir_blocks), dim3(64), 0, s, static_cast<const uint32_t*>(in),
                      static_cast<int8_t*>(work), h->d_taps, h->n_inputs, h->n_frames, s1, runs);
   if (hipGetLastError() != hipSuccess) return CORRX_EDEVICE;
+  const int ni = h->n_inputs % 128 == 0 ? 128 : 64;
   const int64_t tiles =
-      (int64_t)h->n_coarse * (h->n_inputs / kDftInputs) * ((h->n_frames + kDftFrames - 1) / kDftFrames);
+      (int64_t)h->n_coarse * (h->n_inputs / ni) * ((h->n_frames + kDftRows / ni - 1) / (kDftRows / ni));
   if (tiles > (1LL << 30)) return CORRX_EINVAL;  // cannot happen below the input size bound
   // One resident block per compute unit (128 KB of LDS), each walking its
   // tiles with the next one's loads in flight.
   const int64_t grid = tiles < h->n_cu ? tiles : h->n_cu;
-  hipLaunchKernelGGL(fpfb_dft, dim3((unsigned)grid), dim3(512), 0, s, static_cast<const int8_t*>(work),
-                     h->d_wmat, static_cast<uint8_t*>(out), h->n_inputs, h->n_coarse, h->n_frames, s2);
+  if (ni == 128)
+    hipLaunchKernelGGL(fpfb_dft<128>, dim3((unsigned)grid), dim3(512), 0, s, static_cast<const int8_t*>(work),
+                       h->d_wmat, static_cast<uint8_t*>(out), h->n_inputs, h->n_coarse, h->n_frames, s2);
+  else
+    hipLaunchKernelGGL(fpfb_dft<64>, dim3((unsigned)grid), dim3(512), 0, s, static_cast<const int8_t*>(work),
+                       h->d_wmat, static_cast<uint8_t*>(out), h->n_inputs, h->n_coarse, h->n_frames, s2);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 

@@ -45,7 +45,10 @@ def test_tables_equal_the_oracle_definitions(cx):
     fb.close()
 
 
-@pytest.mark.parametrize("n_inputs,n_coarse,n_frames", [(64, 1, 37), (128, 2, 5), (256, 1, 64), (64, 3, 1)])
+# 64-input tiles (N = 64, 192) and 128-input tiles (N = 128, 256, 384), each
+# with a ragged last tile of frames
+@pytest.mark.parametrize("n_inputs,n_coarse,n_frames",
+                         [(64, 1, 37), (128, 2, 5), (256, 1, 64), (64, 3, 1), (192, 1, 6), (384, 1, 3)])
 def test_filterbank_matches_oracle(cx, n_inputs, n_coarse, n_frames):
     import torch
 
