@@ -1,0 +1,148 @@
+"""GPU parity at the benchmarked sizes, in the benchmark's launch
+configuration, on sampled channels that the CPU oracle computes one by one
+(tolerance 0: integer sums).
+
+- full band: 256 inputs x 3072 channels x 10000 samples, TFI, for all three
+  engines, plus the station/polarisation float32 dump of the timed step;
+- one coarse channel: 256 x 128 x 5000, MFMA and plain;
+- the uneven batch: 64/256/512/2048 inputs in one persistent launch.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1501_05992_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FULL = (256, 3072, 10000)
+FULL_CHANNELS = [0, 1, 1000, 2047, 3071]
+COARSE = (256, 128, 5000)
+COARSE_CHANNELS = [0, 17, 64, 127]
+UNEVEN = [(64, 3072, 10000, 0), (256, 768, 5000, 0), (512, 384, 4000, 0), (2048, 128, 2000, 0)]
+
+
+@pytest.fixture(scope="module")
+def cx():
+    import torch
+
+    from paper_1501_05992_amd import corrx
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    corrx.lib()
+    return corrx
+
+
+def _dev():
+    import torch
+
+    return torch.device("cuda:0")
+
+
+class _Problem:
+    """Host input (the benchmark's seed and recipe), its device copy and the
+    oracle's visibilities of the sampled channels, computed once."""
+
+    def __init__(self, oracle_lib, shape, seed, channels):
+        import torch
+
+        self.n, self.fc, self.tc = shape
+        print(f"generating {self.n}x{self.fc}x{self.tc}", flush=True)
+        self.host = synth.make_input(seed, self.n, self.fc, self.tc)
+        self.x = torch.from_numpy(self.host).to(_dev())
+        self.channels = channels
+        self.want = {}
+        for f in channels:
+            ch = np.ascontiguousarray(synth.channel_view(self.host, 0, self.n, self.fc, self.tc, f))
+            self.want[f] = oracle_lib.xmac(ch, self.n, 1, self.tc)[0]
+        print(f"oracle done for channels {channels}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def full_band(oracle_lib):
+    return _Problem(oracle_lib, FULL, synth.config_seed(2), FULL_CHANNELS)
+
+
+@pytest.fixture(scope="module")
+def coarse(oracle_lib):
+    return _Problem(oracle_lib, COARSE, synth.config_seed(1), COARSE_CHANNELS)
+
+
+def _check_sampled(cx, prob, engine):
+    import torch
+
+    c = cx.Correlator(prob.n, prob.fc, prob.tc, cx.CORRX_LAYOUT_TFI, engine)
+    acc = c.new_acc(_dev())
+    c.zero(acc)
+    c.xmac(prob.x, acc)
+    idx = torch.tensor(prob.channels, device=_dev())
+    got = acc.index_select(0, idx).cpu().numpy().astype(np.int64)
+    for k, f in enumerate(prob.channels):
+        assert np.array_equal(got[k], prob.want[f]), f"{engine}: channel {f} differs"
+    return c, acc
+
+
+@pytest.mark.parametrize("engine", ["mfma_i8", "mfma_f8", "plain"])
+def test_full_band_sampled_channels(cx, full_band, engine):
+    print(f"full band, engine {engine}", flush=True)
+    c, acc = _check_sampled(cx, full_band, engine)
+    del acc
+    c.close()
+
+
+def test_full_band_step_dump(cx, oracle_lib, full_band):
+    # the timed step: zero + xmac + station/polarisation float32 dump
+    import torch
+
+    print("full band step with dump", flush=True)
+    c, acc = _check_sampled(cx, full_band, "auto")
+    order = cx.CORRX_TRI_STATION_POL
+    dst = c.dump(acc, order, cx.CORRX_F32)
+    per_chan = dst.numel() // full_band.fc
+    for f in (0, 3071):
+        got = dst[f * per_chan:(f + 1) * per_chan].cpu().numpy()
+        want = oracle_lib.station_pol(full_band.want[f][None], full_band.n).reshape(-1)
+        assert np.array_equal(got, want.astype(np.float32)), f"dump of channel {f} differs"
+    torch.cuda.synchronize()
+    del acc, dst
+    c.close()
+
+
+@pytest.mark.parametrize("engine", ["mfma_i8", "plain"])
+def test_coarse_channel_sampled_channels(cx, coarse, engine):
+    print(f"coarse channel, engine {engine}", flush=True)
+    c, acc = _check_sampled(cx, coarse, engine)
+    del acc
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def uneven(oracle_lib):
+    import torch
+
+    print("generating the uneven batch", flush=True)
+    seed = synth.config_seed(3)
+    hosts = [synth.make_input(seed, n, f, t, array=k) for k, (n, f, t, lay) in enumerate(UNEVEN)]
+    wants = []
+    for (n, f, t, lay), h in zip(UNEVEN, hosts):
+        ch = np.ascontiguousarray(synth.channel_view(h, lay, n, f, t, f - 1))
+        wants.append(oracle_lib.xmac(ch, n, 1, t)[0])
+    print("oracle done for the last channel of each array", flush=True)
+    return [torch.from_numpy(h).to(_dev()) for h in hosts], wants
+
+
+@pytest.mark.parametrize("codes", [None, [0x101, 0x103, 0x103, 0x103]])
+def test_uneven_batch_full_size(cx, uneven, codes):
+    import torch
+
+    print(f"uneven batch, tile codes {codes}", flush=True)
+    ins, wants = uneven
+    b = cx.Batch(UNEVEN, tile_cfg=codes)
+    accs = b.new_accs(_dev())
+    b.zero(accs)
+    b.xmac(ins, accs)
+    torch.cuda.synchronize()
+    for (n, f, t, lay), want, acc in zip(UNEVEN, wants, accs):
+        assert np.array_equal(acc[f - 1].cpu().numpy().astype(np.int64), want), f"array N={n} differs"
+    del accs
+    b.close()
