@@ -5,7 +5,9 @@ configuration, on sampled channels that the CPU oracle computes one by one
 - full band: 256 inputs x 3072 channels x 10000 samples, TFI, for all three
   engines, plus the station/polarisation float32 dump of the timed step;
 - one coarse channel: 256 x 128 x 5000, MFMA and plain;
-- the uneven batch: 64/256/512/2048 inputs in one persistent launch.
+- the uneven batch: 64/256/512/2048 inputs in one persistent launch;
+- the four streaming observations at full channel counts, served together
+  under a tight memory budget and alone.
 """
 
 import numpy as np
@@ -146,3 +148,48 @@ def test_uneven_batch_full_size(cx, uneven, codes):
         assert np.array_equal(acc[f - 1].cpu().numpy().astype(np.int64), want), f"array N={n} differs"
     del accs
     b.close()
+
+
+STREAMS = [("obs256x3072", 256, 3072), ("obs256x768", 256, 768), ("obs512x384", 512, 384), ("obs128x3072", 128, 3072)]
+
+
+def test_streaming_full_shapes_mixed_equals_alone(cx, oracle_lib):
+    # the four streaming observations at their full channel counts, one
+    # 0.5 s integration each, under a budget that holds about two at a time
+    import torch
+
+    from paper_1501_05992_amd.service import CHUNK_SAMPLES, CHUNKS_PER_INTEGRATION, GpuBackend, Observation, Service
+
+    t_int = CHUNK_SAMPLES * CHUNKS_PER_INTEGRATION
+    items = []
+    for k, (name, n, f) in enumerate(STREAMS):
+        print(f"generating {name}", flush=True)
+        host = synth.make_input(synth.config_seed(4), n, f, t_int, array=k)
+        pinned = torch.from_numpy(host).pin_memory()
+        per = n * f * CHUNK_SAMPLES
+        obs = Observation(name, n, f, 1, lambda c, d=pinned, p=per: d[c * p:(c + 1) * p], arrival_s=0.01 * k)
+        items.append((host, obs))
+
+    def serve(subset, budget):
+        svc = Service(GpuBackend(), budget)
+        for _, o in subset:
+            svc.submit(o)
+        st = svc.run(paced=False, keep_outputs=True)
+        return st, {(r.obs_id, r.index): r.output for r in svc.results}
+
+    need = sorted(GpuBackend().mem_bytes(o) for _, o in items)
+    budget = need[-1] + need[-2]
+    st, mixed = serve(items, budget)
+    print(f"mixed: {st['integrations']} integrations, peak {st['peak_hbm_bytes']} of {budget} bytes", flush=True)
+    assert st["integrations"] == len(STREAMS)
+    assert st["peak_hbm_bytes"] <= budget
+    for host, o in items:
+        _, alone = serve([(host, o)], 10 ** 12)
+        assert np.array_equal(mixed[(o.obs_id, 0)], alone[(o.obs_id, 0)]), o.obs_id
+        out = mixed[(o.obs_id, 0)].reshape(o.n_chan, -1)
+        for ch in (0, o.n_chan - 1):
+            vis = oracle_lib.xmac(np.ascontiguousarray(synth.channel_view(host, 0, o.n_inputs, o.n_chan, t_int, ch)),
+                                  o.n_inputs, 1, t_int)
+            want = oracle_lib.station_pol(vis, o.n_inputs).astype(np.float32).reshape(-1)
+            assert np.array_equal(out[ch], want), (o.obs_id, ch)
+        print(f"{o.obs_id}: alone == mixed, channels 0 and {o.n_chan - 1} match the oracle", flush=True)
