@@ -262,8 +262,27 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
     out["uneven_batch"] = uneven_batch(corrx, model, synth, torch, dev, oracle)
     out["pfb_and_output"] = pfb_and_output(corrx, torch, dev, x, n, fc, tc)
     out["fine_pfb"] = fine_pfb(corrx, torch, dev, n, fc // 128)
+    out["incoherent_beam"] = incoherent_beam(corrx, synth, torch, dev, oracle, x, host, n, fc, tc)
     out["streaming"] = streaming(synth, torch)
     return out
+
+
+def incoherent_beam(corrx, synth, torch, dev, oracle, x, host, n, fc, tc):
+    """Incoherent beam over the full band (HBM-bound: the 7.86 GB input read
+    once, one int32 per channel and sample written); channel 0 checked."""
+    c = corrx.Correlator(n, fc, tc)
+    beam = torch.empty((fc, tc), dtype=torch.int32, device=dev)
+    ms = time_ms(torch, lambda: c.beam(x, beam), 5)
+    ok = bool(np.array_equal(beam[0].cpu().numpy().astype(np.int64),
+                             oracle.incoherent_beam(np.ascontiguousarray(synth.channel_view(host, 0, n, fc, tc, 0)),
+                                                    n, 1, tc)[0]))
+    nbytes = x.numel() + beam.numel() * 4
+    res = {"ms": round(ms, 3), "bytes": nbytes, "gbs": round(nbytes / ms / 1e6, 1),
+           "hbm_frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 3), "channel0_bit_exact": ok}
+    log(f"incoherent beam: {ms:.3f} ms ({res['gbs']} GB/s)")
+    del beam
+    c.close()
+    return res
 
 
 def time_ms(torch, fn, reps):

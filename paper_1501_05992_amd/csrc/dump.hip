@@ -249,9 +249,10 @@ int launch_pfb_remap(const int* src, int* dst, int n_inputs, int n_chan, hipStre
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
-// Incoherent beam: out[f][t] = sum_i |x_i(f,t)|^2.  One thread per (f, t)
-// row; four samples per dword through the biased parts u = re + 8, w = im + 8:
+// Incoherent beam: out[f][t] = sum_i |x_i(f,t)|^2, four samples per dword
+// through the biased parts u = re + 8, w = im + 8:
 //     re^2 + im^2 = u^2 + w^2 - 16 (u + w) + 128.
+// General path (any N and alignment): one thread per (f, t) row.
 __global__ void beam_rows(Problem p, int* out, int64_t nrows) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const bool aligned = (p.n_inputs % 4 == 0) && ((reinterpret_cast<uintptr_t>(p.in) & 3) == 0);
@@ -280,10 +281,137 @@ __global__ void beam_rows(Problem p, int* out, int64_t nrows) {
   }
 }
 
+// Fast path (N a multiple of 16, 16-byte aligned input): 16 lanes per input
+// row, each lane one 16-byte load per 256 bytes of the row, then a 16-lane
+// reduction, so that one wave load covers four whole rows.  partial16 gives
+// sum (u^2 + w^2 - 16 (u + w)) over the 16 samples of one load; the row adds
+// 128 N.  Invalid samples are masked in a branch only such loads take.
+__device__ inline int beam_partial16(uint4 v) {
+  uint32_t y[4] = {bias4(v.x), bias4(v.y), bias4(v.z), bias4(v.w)};
+  if (invalid_flags(y[0]) | invalid_flags(y[1]) | invalid_flags(y[2]) | invalid_flags(y[3])) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y[k] = mask_invalid(y[k]);
+  }
+  uint32_t sq = 0, lin = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t u = bre4(y[k]), w = bim4(y[k]);
+    sq = __builtin_amdgcn_udot4(u, u, sq, false);
+    sq = __builtin_amdgcn_udot4(w, w, sq, false);
+    lin = bytesum(u + w, lin);  // u + w <= 30: no carry between bytes
+  }
+  return (int)(sq - 16u * lin);
+}
+
+__device__ inline int beam_reduce16(int part, int n_inputs) {
+  part += __shfl_xor(part, 8, 16);
+  part += __shfl_xor(part, 4, 16);
+  part += __shfl_xor(part, 2, 16);
+  part += __shfl_xor(part, 1, 16);
+  return part + 128 * n_inputs;
+}
+
+// Rows r0, r0 + 16, .., r0 + 16 (R - 1) of this lane's group: all loads are
+// issued before any arithmetic.  SMALL (N <= 256): one load per lane and
+// row; otherwise a loop over the row's 256-byte pieces.
+template <bool SMALL, int R, class RowPtr>
+__device__ inline void beam_rows_batch(const RowPtr& row_of, int r0, int n_inputs, int l, int (&v)[R]) {
+  if constexpr (SMALL) {
+    uint4 x[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      x[k] = 16 * l < n_inputs ? *reinterpret_cast<const uint4*>(row_of(r0 + 16 * k) + 16 * l) : uint4{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = beam_reduce16(16 * l < n_inputs ? beam_partial16(x[k]) : 0, n_inputs);
+  } else {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint8_t* row = row_of(r0 + 16 * k);
+      int part = 0;
+      for (int i = 16 * l; i < n_inputs; i += 256) part += beam_partial16(*reinterpret_cast<const uint4*>(row + i));
+      v[k] = beam_reduce16(part, n_inputs);
+    }
+  }
+}
+
+constexpr int kBeamTile = 64;
+constexpr int kBeamBatch = 8;  // rows in flight per 16-lane group
+
+// TFI: a block takes 64 channels x 64 times; row (t0 + j, f0 + a) for
+// r = 64 j + a, so that neighbouring groups read neighbouring rows; the
+// results go through LDS and leave as contiguous runs of out[f][t0 .. t0+63].
+template <bool SMALL>
+__global__ __launch_bounds__(256) void beam_tfi(Problem p, int* out, int nfb) {
+  __shared__ int tile[kBeamTile][kBeamTile + 1];
+  const int fb = blockIdx.x % nfb, tb = blockIdx.x / nfb;
+  const int f0 = fb * kBeamTile, t0 = tb * kBeamTile;
+  const int nf = min(kBeamTile, p.n_chan - f0), nt = min(kBeamTile, p.n_time - t0);
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  // rows outside the array (ragged tiles) read the tile's first row instead
+  auto row_of = [&](int r) {
+    const int a = r % kBeamTile, j = r / kBeamTile;
+    const int64_t m = a < nf && j < nt ? (int64_t)(t0 + j) * p.n_chan + f0 + a : (int64_t)t0 * p.n_chan + f0;
+    return p.in + m * p.n_inputs;
+  };
+  for (int r0 = g; r0 < kBeamTile * kBeamTile; r0 += 16 * kBeamBatch) {
+    int v[kBeamBatch];
+    beam_rows_batch<SMALL>(row_of, r0, p.n_inputs, l, v);
+    if (l == 0) {
+#pragma unroll
+      for (int k = 0; k < kBeamBatch; ++k) {
+        const int r = r0 + 16 * k;
+        tile[r % kBeamTile][r / kBeamTile] = v[k];
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kBeamTile * kBeamTile; idx += 256) {
+    const int a = idx / kBeamTile, j = idx % kBeamTile;
+    if (a < nf && j < nt) out[(int64_t)(f0 + a) * p.n_time + t0 + j] = tile[a][j];
+  }
+}
+
+// FTI: memory row m = f T + t is also the output index.  Rows past the end
+// read the last row and are not stored.
+template <bool SMALL>
+__global__ __launch_bounds__(256) void beam_fti(Problem p, int* out, int64_t nrows) {
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  const int64_t step = (int64_t)gridDim.x * 16 * kBeamBatch;
+  for (int64_t m0 = (int64_t)blockIdx.x * 16 * kBeamBatch; m0 < nrows; m0 += step) {
+    auto row_of = [&](int r) { return p.in + min(m0 + r, nrows - 1) * p.n_inputs; };
+    int v[kBeamBatch];
+    beam_rows_batch<SMALL>(row_of, g, p.n_inputs, l, v);
+    if (l == 0) {
+#pragma unroll
+      for (int k = 0; k < kBeamBatch; ++k)
+        if (m0 + g + 16 * k < nrows) out[m0 + g + 16 * k] = v[k];
+    }
+  }
+}
+
 int launch_beam(const Problem& p, int* out, hipStream_t s) {
   const int64_t nrows = (int64_t)p.n_chan * p.n_time;
-  const int grid = (int)((nrows + 255) / 256 < 16384 ? (nrows + 255) / 256 : 16384);
-  hipLaunchKernelGGL(beam_rows, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, p, out, nrows);
+  if (nrows == 0) return CORRX_OK;
+  const bool fast = p.n_inputs % 16 == 0 && (reinterpret_cast<uintptr_t>(p.in) & 15) == 0;
+  const bool small = p.n_inputs <= 256;
+  if (fast && p.layout == CORRX_LAYOUT_TFI) {
+    const int64_t nfb = (p.n_chan + kBeamTile - 1) / kBeamTile, ntb = (p.n_time + kBeamTile - 1) / kBeamTile;
+    if (nfb * ntb > 0x7FFFFFFF) return CORRX_EINVAL;
+    if (small)
+      hipLaunchKernelGGL(beam_tfi<true>, dim3((unsigned)(nfb * ntb)), dim3(256), 0, s, p, out, (int)nfb);
+    else
+      hipLaunchKernelGGL(beam_tfi<false>, dim3((unsigned)(nfb * ntb)), dim3(256), 0, s, p, out, (int)nfb);
+  } else if (fast) {
+    const int64_t blocks = (nrows + 16 * kBeamBatch - 1) / (16 * kBeamBatch);
+    const unsigned grid = (unsigned)(blocks < 65536 ? blocks : 65536);
+    if (small)
+      hipLaunchKernelGGL(beam_fti<true>, dim3(grid), dim3(256), 0, s, p, out, nrows);
+    else
+      hipLaunchKernelGGL(beam_fti<false>, dim3(grid), dim3(256), 0, s, p, out, nrows);
+  } else {
+    const int grid = (int)((nrows + 255) / 256 < 16384 ? (nrows + 255) / 256 : 16384);
+    hipLaunchKernelGGL(beam_rows, dim3(grid), dim3(256), 0, s, p, out, nrows);
+  }
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 

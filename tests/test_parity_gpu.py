@@ -189,15 +189,20 @@ def test_zero_resets_and_overflow_guard(cx):
     c.close()
 
 
-def test_beam(cx, oracle_lib):
+# 16-lane rows with a 64 x 64 tile transpose (TFI) or direct rows (FTI) when
+# N % 16 == 0; one thread per row otherwise.  Shapes cover whole and ragged
+# tiles, N below, at and above 256, and invalid codes.
+@pytest.mark.parametrize("n,fc,tc,layout", [(256, 4, 500, 0), (256, 64, 128, 0), (48, 70, 65, 0), (512, 3, 130, 0),
+                                            (256, 5, 77, 1), (320, 2, 40, 1), (7, 3, 50, 0), (100, 2, 33, 1)])
+def test_beam(cx, oracle_lib, n, fc, tc, layout):
     import torch
 
-    n, fc, tc = 256, 4, 500
-    buf = synth.make_input(7000, n, fc, tc)
+    buf = synth.make_input(7000 + n, n, fc, tc, layout=layout)
     buf[:100] = 0x88
-    c = cx.Correlator(n, fc, tc)
+    buf[1000:1040] = 0x80  # invalid real part: contributes nothing
+    c = cx.Correlator(n, fc, tc, layout)
     out = c.beam(torch.from_numpy(buf).cuda()).cpu().numpy()
-    assert np.array_equal(out.astype(np.int64), oracle_lib.incoherent_beam(buf, n, fc, tc))
+    assert np.array_equal(out.astype(np.int64), oracle_lib.incoherent_beam(buf, n, fc, tc, layout))
     c.close()
 
 
