@@ -50,8 +50,8 @@ __device__ inline v2s pair16(uint32_t lo_word, uint32_t hi_word) {
 // in 128..255 (the GEMM's K axis).  The 12-tap sums run as 6 packed int16
 // dot products over tap pairs (j, j + 1), the samples of frames m and m + 1
 // paired the same way.
-__global__ __launch_bounds__(64) void fpfb_fir(const uint32_t* in, int8_t* work, const int16_t* taps, int n_inputs,
-                                               int n_frames, int s1, int runs) {
+__global__ __launch_bounds__(64) void fpfb_fir(const uint32_t* in, int8_t* work, const int16_t* taps, int n_frames,
+                                               int s1, int runs) {
   const int p = 2 * threadIdx.x;
   const int run = blockIdx.x % runs;
   const int ci = blockIdx.x / runs;  // c * n_inputs + i
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(64) void fpfb_fir(const uint32_t* in, int8_t* work,
   }
 }
 
-// GEMM geometry: 256 rows (row = k_l * 64 + i_l) x 256 columns (0..127 re q,
+// GEMM geometry: 256 rows (row = k_l NI + i_l) x 256 columns (0..127 re q,
 // 128..255 im q) x K = 256; 8 waves as 2 x 4 tiles of 128 x 64.
 __device__ inline int swz16(int row) { return (row ^ (row >> 2)) & 15; }
 // Granule swizzle of the transposed codes (one 256-byte row per output
@@ -366,7 +366,7 @@ int corr_fpfb(corrx_fpfb_t h, const void* in, int s1, int s2, void* work, void* 
   const int64_t fir_blocks = (int64_t)h->n_coarse * h->n_inputs * runs;
   if (fir_blocks > 0x7FFFFFFF) return CORRX_EINVAL;
   hipLaunchKernelGGL(fpfb_fir, dim3((unsigned)fir_blocks), dim3(64), 0, s, static_cast<const uint32_t*>(in),
-                     static_cast<int8_t*>(work), h->d_taps, h->n_inputs, h->n_frames, s1, runs);
+                     static_cast<int8_t*>(work), h->d_taps, h->n_frames, s1, runs);
   if (hipGetLastError() != hipSuccess) return CORRX_EDEVICE;
   const int ni = h->n_inputs % 128 == 0 ? 128 : 64;
   const int64_t tiles =
