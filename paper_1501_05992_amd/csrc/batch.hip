@@ -84,13 +84,17 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
     if (d.layout != CORRX_LAYOUT_TFI && d.layout != CORRX_LAYOUT_FTI) return CORRX_EINVAL;
     if ((double)d.n_inputs * d.n_chan * d.n_time >= 1099511627776.0) return CORRX_EINVAL;
     const int64_t stride = d.layout == CORRX_LAYOUT_TFI ? (int64_t)d.n_chan * d.n_inputs : d.n_inputs;
-    if (d.n_inputs % 4 != 0 || 128 * stride + d.n_inputs >= 0x7FFFFFFF) return CORRX_EUNSUPPORTED;
+    const int unit = tile_cfg ? (tile_cfg[a] & 0xFF) : CORRX_TILE_DEFAULT;
     if (tile_cfg) {
-      const int unit = tile_cfg[a] & 0xFF, spl = (tile_cfg[a] >> 8) & 0xFFFF;
+      const int spl = (tile_cfg[a] >> 8) & 0xFFFF;
       if (unit > CORRX_TILE_UNIT256 || spl > 4096) return CORRX_EINVAL;
       if ((unit == CORRX_TILE_UNIT64 && d.n_inputs > 64) || (unit == CORRX_TILE_UNIT128 && d.n_inputs > 128))
         return CORRX_EINVAL;
     }
+    // one chunk of rows (256 for 64-input units, else 128 at most) must span
+    // less than 2^31 bytes
+    const bool unit64 = unit == CORRX_TILE_UNIT64 || (unit == CORRX_TILE_DEFAULT && d.n_inputs <= 64);
+    if (d.n_inputs % 4 != 0 || (unit64 ? 256 : 128) * stride + d.n_inputs >= 0x7FFFFFFF) return CORRX_EUNSUPPORTED;
   }
   int dev = 0, n_cu = 0;
   if (!gfx950(&dev, &n_cu)) return CORRX_EDEVICE;

@@ -70,7 +70,7 @@ struct Stage {
   static constexpr int BYTES = ROWS * ROWB;          // one stage buffer
   static constexpr int GRAN = ROWB / 16;             // 16-byte granules per row and chunk
   static constexpr int KSTEPS = TC / 16;             // K=32 (16-sample) MFMA steps per chunk
-  static_assert(TC == 64 || TC == 128, "the unpack is split into four phases over the K-steps of a chunk");
+  static_assert(TC == 64 || TC == 128 || TC == 256, "the unpack is split into four phases over the K-steps of a chunk");
   static constexpr bool FP8 = false;
 
   // Stage quad q -> first input: the first `split` quads start at base0, the
@@ -103,7 +103,7 @@ struct Stage {
       // (scalar arithmetic) and whose range ends at the channel's last valid
       // row, so the per-lane offset is the same for all 8 rows of the item.
       const int rows = min(t1 - tb, TC);
-      // 128 rows of a channel span less than 2^31 bytes (checked on the host),
+      // TC rows of a channel span less than 2^31 bytes (checked on the host),
       // so the range arithmetic stays in 32-bit scalar registers.
       const int stride32 = (int)stride;
       const int nrec0 = (rows - 1) * stride32 + p.n_inputs;
@@ -356,13 +356,14 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
 
 // ---- diagonal unit -----------------------------------------------------------
 
-// Samples per chunk of a diagonal unit.  (128 would halve the barriers per
-// sample, but the extra loads in flight exceed the registers of two waves
-// per SIMD.)
+// Samples per chunk of a standalone diagonal unit.  64 for 128 and 256 inputs
+// (128 would halve the barriers per sample, but the extra loads in flight
+// exceed the registers of two waves per SIMD); 128 for 64 inputs, whose units
+// are HBM-bound and have registers to spare.
 template <int NB>
-constexpr int diag_tc = 64;
+constexpr int diag_tc = NB == 64 ? 128 : 64;
 
-template <int NB, int WC>
+template <int NB, int WC, int TC_ = diag_tc<NB>>
 struct DiagGeom {
   static constexpr int WR = 2;                       // wave rows
   static constexpr int NW = WR * WC;                 // waves
@@ -374,7 +375,7 @@ struct DiagGeom {
   static constexpr int H = NB / 2;                   // quadrant side
   static constexpr int XPITCH = H + 1;
   static constexpr int XAREA = H * XPITCH;           // int32 words of one exchange area
-  static constexpr int TC = diag_tc<NB>;             // samples per chunk
+  static constexpr int TC = TC_;                     // samples per chunk
   static constexpr int STAGE = NB * 2 * TC;          // one stage buffer
   static constexpr int LDS = (2 * STAGE > 2 * XAREA * 4) ? 2 * STAGE : 2 * XAREA * 4;
   static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tiles are made of 32x32 MFMA tiles");
@@ -425,14 +426,14 @@ __device__ inline void combine_quadrant(const Problem& p, int f, int ibase, cons
 // One diagonal unit: inputs ibase .. ibase+NB-1 of channel f over samples
 // [t0, t1), run by the NT threads whose local index is tid.  lds: G::LDS
 // bytes; s_sy, s_sw: NB words each.
-template <int NB, int WC, bool ALIGNED>
+template <int NB, int WC, bool ALIGNED, int TC = diag_tc<NB>>
 __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int tid, uint8_t* lds, uint32_t* s_sy,
                          uint32_t* s_sw, int mode) {
   // Values derived from the thread index are recomputed for every unit: when
   // units run in a loop (the persistent kernel), hoisting them out of it would
   // keep them live across the whole unit and exhaust the registers.
   asm volatile("" : "+v"(tid));
-  using G = DiagGeom<NB, WC>;
+  using G = DiagGeom<NB, WC, TC>;
   using S = Stage<NB, G::TC, G::NT>;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WC, wc = wave % WC;
@@ -907,7 +908,12 @@ int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg
 
 constexpr int kBatchLds =
     DiagGeom<256, 4>::LDS > PairGeom::LDS ? DiagGeom<256, 4>::LDS : PairGeom::LDS;
+// The batch's 64-input units take 256-sample chunks: with only two units per
+// compute unit (one workgroup of 512 threads), the longer chunks keep four
+// times as many input bytes in flight per unit as 64-sample chunks.
+constexpr int kBatchTc64 = 256;
 static_assert(2 * DiagGeom<128, 2>::LDS <= kBatchLds, "two 128-input units fit side by side");
+static_assert(2 * DiagGeom<64, 2, kBatchTc64>::LDS <= kBatchLds, "two 64-input units fit side by side");
 
 // Next work item of the persistent kernel (same value in every thread).
 __device__ inline int batch_fetch(int* counter, int* s_item) {
@@ -946,8 +952,10 @@ __device__ __noinline__ int batch_small_run(const Problem* table, const WorkItem
     const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
     const int tid = threadIdx.x;
     const int g = tid >> 8, f = w.channel + g;
-    run_diag<NB, 2, true>(p, min(f, p.n_chan - 1), 0, w.t0, w.t1, tid & 255, lds + g * DiagGeom<NB, 2>::LDS,
-                          s_sy + NB * g, s_sw + NB * g, f < p.n_chan ? mode : (int)kWriteNone);
+    constexpr int TC = NB == 64 ? kBatchTc64 : diag_tc<NB>;
+    run_diag<NB, 2, true, TC>(p, min(f, p.n_chan - 1), 0, w.t0, w.t1, tid & 255,
+                              lds + g * DiagGeom<NB, 2, TC>::LDS, s_sy + NB * g, s_sw + NB * g,
+                              f < p.n_chan ? mode : (int)kWriteNone);
     it = batch_fetch(counter, s_item);
   }
   return it;
