@@ -36,9 +36,9 @@ KERNEL_SOURCES = ("paper_1501_05992_amd/csrc/xengine_mfma.hip",
                   "paper_1501_05992_amd/csrc/corrx_internal.h",
                   "paper_1501_05992_amd/csrc/api.hip")
 TRAFFIC = {
-    "sources_sha256": "99aed5609c91b471923fa335db6388058920d6f12404e67569e4958414c0f130",
-    "read_bytes": 7864107446,   # FETCH_SIZE 3,840,245 KiB x 2.000
-    "write_bytes": 832998197,   # WRITE_SIZE 813,475 KiB x 1.000
+    "sources_sha256": "98a6c9074e9d8c4884146cd87244a2f044851ebae811031b5c7e93e45361f791",
+    "read_bytes": 7864085372,   # FETCH_SIZE 3,840,243 KiB x 2.000
+    "write_bytes": 833006571,   # WRITE_SIZE 813,483 KiB x 1.000
     "summary": "profiles/xmac_diag_i8_full_band_256x3072x10000_traffic.txt",
 }
 
