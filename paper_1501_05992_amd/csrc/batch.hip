@@ -122,9 +122,11 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
     total += (double)items * item_cost(kind, d.n_inputs, d.n_time);
   }
   // Time splits per array: requested, or enough that no item costs more than
-  // 1/8 of a compute unit's fair share (load balance of the longest-first
+  // half of a compute unit's fair share (load balance of the longest-first
   // schedule), with at least 512 samples per split and at most kMaxUnitTime.
-  const double target = total / (8.0 * n_cu);
+  // Splits are not free: a split item adds its output with atomics, which
+  // costs more than the imbalance of a few whole items per compute unit.
+  const double target = total / (2.0 * n_cu);
   std::vector<WorkItem> items;
   for (int a = 0; a < n; ++a) {
     const corrx_desc& d = descs[a];
