@@ -36,9 +36,9 @@ KERNEL_SOURCES = ("paper_1501_05992_amd/csrc/xengine_mfma.hip",
                   "paper_1501_05992_amd/csrc/corrx_internal.h",
                   "paper_1501_05992_amd/csrc/api.hip")
 TRAFFIC = {
-    "sources_sha256": "98a6c9074e9d8c4884146cd87244a2f044851ebae811031b5c7e93e45361f791",
-    "read_bytes": 7864085372,   # FETCH_SIZE 3,840,243 KiB x 2.000
-    "write_bytes": 833006571,   # WRITE_SIZE 813,483 KiB x 1.000
+    "sources_sha256": "2fbe8929503acc3cc057d05fb4b7cad257b9f5cee58cb3ede71b74fc2d7950d3",
+    "read_bytes": 7864112977,   # FETCH_SIZE 3,840,242 KiB x 2.000
+    "write_bytes": 832990826,   # WRITE_SIZE 813,468 KiB x 1.000
     "summary": "profiles/xmac_diag_i8_full_band_256x3072x10000_traffic.txt",
 }
 

@@ -33,12 +33,15 @@ bool device_ok(int* dev, int* n_cu) {
 
 int resolve_engine(int e) { return e == CORRX_ENGINE_AUTO ? CORRX_ENGINE_MFMA_I8 : e; }
 
-// Time splits per channel: enough work units to fill the chip (about two per
-// compute unit), at least 512 samples per split, at most kMaxUnitTime.
-int plan_splits(int n_chan, int units_per_chan, int n_time, int n_cu, int max_unit = kMaxUnitTime) {
+// Time splits per channel: enough work units to reach `target` (at least 512
+// samples per split, at most max_unit per unit).  A split unit adds its output
+// with atomics, so units with a large output (256-input blocks: 263 KB per
+// channel) split only while fewer than half the compute units would have work;
+// small units (64/128-input blocks, the plain engine's 64 x 64 tiles) aim at
+// about two per compute unit.
+int plan_splits(int n_chan, int units_per_chan, int n_time, int64_t target, int max_unit = kMaxUnitTime) {
   const int64_t units = (int64_t)n_chan * units_per_chan;
   int split = 1;
-  const int64_t target = 2LL * n_cu;
   while (units * split < target && n_time / (2 * split) >= 512) split *= 2;
   while ((n_time + split - 1) / split > max_unit) ++split;
   return split;
@@ -149,12 +152,14 @@ int corr_xmac(corrx_t h, const void* in, void* acc, void* stream) {
   int rc;
   if (engine == CORRX_ENGINE_PLAIN) {
     const int nbk = (h->n_inputs + 63) / 64;
-    rc = launch_plain(p, plan_splits(h->n_chan, nbk * (nbk + 1) / 2, h->n_time, h->n_cu), mode,
+    rc = launch_plain(p, plan_splits(h->n_chan, nbk * (nbk + 1) / 2, h->n_time, 2LL * h->n_cu), mode,
                       as_stream(stream));
   } else {
     const int units = engine == CORRX_ENGINE_MFMA_F8 ? 1 : mfma_units_per_channel(h->n_inputs);
     const int max_unit = engine == CORRX_ENGINE_MFMA_F8 ? kMaxUnitTimeF8 : kMaxUnitTime;
-    rc = launch_mfma(p, engine, plan_splits(h->n_chan, units, h->n_time, h->n_cu, max_unit), mode,
+    const bool large = engine == CORRX_ENGINE_MFMA_F8 || h->n_inputs > 128;
+    const int64_t target = large ? h->n_cu / 2 : 2LL * h->n_cu;
+    rc = launch_mfma(p, engine, plan_splits(h->n_chan, units, h->n_time, target, max_unit), mode,
                      CORRX_TILE_DEFAULT, as_stream(stream));
   }
   if (rc == CORRX_OK) h->samples += h->n_time;
