@@ -128,11 +128,24 @@ def _check(rc: int, what: str) -> int:
     return rc
 
 
-def _ptr(t) -> int | None:
+def _ptr(t, nbytes: int | None = None, what: str = "buffer") -> int | None:
+    """Device address of a tensor; a raw integer address passes through.
+
+    The library takes plain pointers and cannot check them, so a tensor must
+    be on a GPU, contiguous, and (when nbytes is given) at least nbytes long;
+    anything else raises ValueError before the call.
+    """
     if t is None:
         return None
     if isinstance(t, int):
         return t
+    if not t.is_cuda:
+        raise ValueError(f"{what}: a GPU tensor is required, got one on {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: the tensor must be contiguous")
+    have = t.numel() * t.element_size()
+    if nbytes is not None and have < nbytes:
+        raise ValueError(f"{what}: {have} bytes, at least {nbytes} needed")
     return t.data_ptr()
 
 
@@ -177,30 +190,35 @@ def corr_samples(h: int) -> int:
 
 
 def corr_zero(h: int, acc, stream=None) -> None:
-    _check(lib().corr_zero(h, _ptr(acc), _stream(stream)), "corr_zero")
+    _check(lib().corr_zero(h, _ptr(acc, corr_acc_bytes(h), "acc"), _stream(stream)), "corr_zero")
 
 
 def corr_xmac(h: int, inp, acc, stream=None) -> None:
-    _check(lib().corr_xmac(h, _ptr(inp), _ptr(acc), _stream(stream)), "corr_xmac")
+    _check(lib().corr_xmac(h, _ptr(inp, what="input"), _ptr(acc, corr_acc_bytes(h), "acc"), _stream(stream)),
+           "corr_xmac")
 
 
 def corr_dump(h: int, acc, order: int, dtype: int, dst, stream=None) -> None:
-    _check(lib().corr_dump(h, _ptr(acc), order, dtype, _ptr(dst), _stream(stream)), "corr_dump")
+    n = corr_dump_count(h, order)
+    _check(lib().corr_dump(h, _ptr(acc, corr_acc_bytes(h), "acc"), order, dtype,
+                           _ptr(dst, 4 * n if n > 0 else None, "dst"), _stream(stream)), "corr_dump")
 
 
 def corr_dump_avg(h: int, acc, order: int, dtype: int, f_avg: int, t_avg: int, dst, stream=None) -> None:
-    _check(lib().corr_dump_avg(h, _ptr(acc), order, dtype, f_avg, t_avg, _ptr(dst), _stream(stream)),
-           "corr_dump_avg")
+    _check(lib().corr_dump_avg(h, _ptr(acc, corr_acc_bytes(h), "acc"), order, dtype, f_avg, t_avg,
+                               _ptr(dst, what="dst"), _stream(stream)), "corr_dump_avg")
 
 
 def corr_pfb_ingest(h: int, lanes, order: int, inp, stream=None) -> None:
     n = len(lanes)
-    pl = (ctypes.c_void_p * n)(*[_ptr(x) for x in lanes])
-    _check(lib().corr_pfb_ingest(h, pl, order, _ptr(inp), _stream(stream)), "corr_pfb_ingest")
+    pl = (ctypes.c_void_p * n)(*[_ptr(x, what="lane") for x in lanes])
+    _check(lib().corr_pfb_ingest(h, pl, order, _ptr(inp, what="input"), _stream(stream)), "corr_pfb_ingest")
 
 
 def corr_pfb_remap(h: int, acc_pkt, acc_nat, stream=None) -> None:
-    _check(lib().corr_pfb_remap(h, _ptr(acc_pkt), _ptr(acc_nat), _stream(stream)), "corr_pfb_remap")
+    nb = corr_acc_bytes(h)
+    _check(lib().corr_pfb_remap(h, _ptr(acc_pkt, nb, "acc_pkt"), _ptr(acc_nat, nb, "acc_nat"), _stream(stream)),
+           "corr_pfb_remap")
 
 
 def corr_fpfb_create(n_inputs: int, n_coarse: int, n_frames: int) -> int:
@@ -226,11 +244,12 @@ def corr_fpfb_tables(h: int):
 
 
 def corr_fpfb(h: int, inp, s1: int, s2: int, work, out, stream=None) -> None:
-    _check(lib().corr_fpfb(h, _ptr(inp), s1, s2, _ptr(work), _ptr(out), _stream(stream)), "corr_fpfb")
+    _check(lib().corr_fpfb(h, _ptr(inp, what="input"), s1, s2, _ptr(work, corr_fpfb_workspace_bytes(h), "work"),
+                           _ptr(out, what="out"), _stream(stream)), "corr_fpfb")
 
 
 def corr_beam(h: int, inp, out, stream=None) -> None:
-    _check(lib().corr_beam(h, _ptr(inp), _ptr(out), _stream(stream)), "corr_beam")
+    _check(lib().corr_beam(h, _ptr(inp, what="input"), _ptr(out, what="out"), _stream(stream)), "corr_beam")
 
 
 def corr_batch_create(descs, engine: int = CORRX_ENGINE_AUTO, tile_cfg=None) -> int:
@@ -260,14 +279,14 @@ def corr_batch_plan(b: int, array: int) -> tuple[int, int]:
 
 def corr_batch_zero(b: int, accs, stream=None) -> None:
     n = len(accs)
-    pacc = (ctypes.c_void_p * n)(*[_ptr(x) for x in accs])
+    pacc = (ctypes.c_void_p * n)(*[_ptr(x, what="acc") for x in accs])
     _check(lib().corr_batch_zero(b, pacc, _stream(stream)), "corr_batch_zero")
 
 
 def corr_batch_xmac(b: int, ins, accs, stream=None) -> None:
     n = len(ins)
-    pin = (ctypes.c_void_p * n)(*[_ptr(x) for x in ins])
-    pacc = (ctypes.c_void_p * n)(*[_ptr(x) for x in accs])
+    pin = (ctypes.c_void_p * n)(*[_ptr(x, what="input") for x in ins])
+    pacc = (ctypes.c_void_p * n)(*[_ptr(x, what="acc") for x in accs])
     _check(lib().corr_batch_xmac(b, pin, pacc, _stream(stream)), "corr_batch_xmac")
 
 
@@ -310,6 +329,7 @@ class Correlator:
         corr_zero(self.h, acc, stream)
 
     def xmac(self, inp, acc, stream=None) -> None:
+        _ptr(inp, self.n_inputs * self.n_chan * self.n_time, "input")
         corr_xmac(self.h, inp, acc, stream)
 
     def dump(self, acc, order: int = CORRX_TRI_INPUT, dtype: int = CORRX_I32, dst=None, stream=None):
@@ -330,6 +350,9 @@ class Correlator:
         return dst
 
     def pfb_ingest(self, lanes, order: int = CORRX_ORDER_NATURAL, inp=None, stream=None):
+        if self.n_chan % 128 == 0:
+            for x in lanes:
+                _ptr(x, (self.n_chan // 128) * 4 * self.n_time * 256, "lane")
         if inp is None:
             inp = torch.empty(self.n_time * self.n_chan * self.n_inputs, dtype=torch.uint8,
                               device=lanes[0].device)
@@ -345,6 +368,8 @@ class Correlator:
     def beam(self, inp, out=None, stream=None):
         if out is None:
             out = torch.empty((self.n_chan, self.n_time), dtype=torch.int32, device=inp.device)
+        _ptr(inp, self.n_inputs * self.n_chan * self.n_time, "input")
+        _ptr(out, 4 * self.n_chan * self.n_time, "out")
         corr_beam(self.h, inp, out, stream)
         return out
 
@@ -387,6 +412,8 @@ class FineFilterbank:
             self._work = torch.empty(corr_fpfb_workspace_bytes(self.h), dtype=torch.uint8, device=dev)
         if out is None:
             out = torch.empty(self.n_frames * 128 * self.n_coarse * self.n_inputs, dtype=torch.uint8, device=dev)
+        _ptr(inp, 2 * self.n_inputs * self.n_coarse * self.n_samples, "input")
+        _ptr(out, self.n_frames * 128 * self.n_coarse * self.n_inputs, "out")
         corr_fpfb(self.h, inp, s1, s2, self._work, out, stream)
         return out
 
@@ -420,8 +447,20 @@ class Batch:
         return [torch.zeros((f, n * (n + 1) // 2, 2), dtype=torch.int32, device=device)
                 for (n, f, t, lay) in self.descs]
 
+    def _check_accs(self, accs) -> None:
+        if len(accs) != len(self.descs):
+            raise ValueError(f"{len(accs)} accumulators for {len(self.descs)} arrays")
+        for (n, f, t, lay), a in zip(self.descs, accs):
+            _ptr(a, 8 * f * (n * (n + 1) // 2), "acc")
+
     def zero(self, accs, stream=None) -> None:
+        self._check_accs(accs)
         corr_batch_zero(self.h, accs, stream)
 
     def xmac(self, ins, accs, stream=None) -> None:
+        self._check_accs(accs)
+        if len(ins) != len(self.descs):
+            raise ValueError(f"{len(ins)} inputs for {len(self.descs)} arrays")
+        for (n, f, t, lay), x in zip(self.descs, ins):
+            _ptr(x, n * f * t, "input")
         corr_batch_xmac(self.h, ins, accs, stream)

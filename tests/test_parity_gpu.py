@@ -286,3 +286,27 @@ def test_fp8_rejects_large_arrays(cx):
         c.xmac(x, acc)
     assert e.value.status == cx.CORRX_EUNSUPPORTED
     c.close()
+
+
+def test_binding_rejects_host_short_and_strided_buffers(cx):
+    # the library takes plain device pointers; the binding checks tensors first
+    import torch
+
+    c = cx.Correlator(64, 2, 10)
+    acc = c.new_acc()
+    x = torch.zeros(64 * 2 * 10, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        c.xmac(x.cpu(), acc)  # host memory
+    with pytest.raises(ValueError):
+        c.xmac(x[:-1], acc)  # one byte short
+    with pytest.raises(ValueError):
+        c.xmac(x, acc[:, :-1])  # short accumulator
+    with pytest.raises(ValueError):
+        c.zero(torch.zeros((acc.shape[1], 2, 2), dtype=torch.int32, device="cuda").transpose(0, 1))  # strided
+    with pytest.raises(ValueError):
+        c.dump(acc, cx.CORRX_TRI_INPUT, cx.CORRX_I32, dst=torch.empty(10, dtype=torch.int32, device="cuda"))
+    c.zero(acc)
+    c.xmac(x, acc)
+    torch.cuda.synchronize()
+    assert int(acc.abs().sum()) == 0  # byte 0x00 is the sample 0 + 0j
+    c.close()
