@@ -242,8 +242,10 @@ int64_t corr_samples(corrx_t h);
 
 /*
  * Incoherent beam (Sec. 3.4, other XMAC modes): out[f][t] = sum_i |x_i(f,t)|^2
- * as int32 for the handle's shape.  in: device, as for corr_xmac; out: device,
- * n_chan * n_time * 4 bytes.
+ * as int32 for the handle's shape; invalid samples contribute nothing.
+ * in: device, as for corr_xmac; out: device, n_chan * n_time * 4 bytes,
+ * [f][t].  Any N and alignment; N a multiple of 16 with a 16-byte aligned
+ * input takes the fast path (whole rows per 16 lanes).
  */
 int corr_beam(corrx_t h, const void *in, void *out, void *stream);
 
