@@ -89,6 +89,15 @@ def test_ragged_time(cx, oracle_lib, engine, tc):
     _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} T={tc}")
 
 
+@pytest.mark.parametrize("n,layout", [(64, 0), (40, 1)])
+@pytest.mark.parametrize("tc", [1, 127, 128, 129, 1000, 4097])
+def test_ragged_time_small_units(cx, oracle_lib, n, layout, tc):
+    # 64-input units take 128-sample chunks
+    fc = 3
+    buf = synth.make_input(2500 + tc, n, fc, tc, layout=layout)
+    _compare(_run(cx, buf, n, fc, tc, layout), oracle_lib.xmac(buf, n, fc, tc, layout), n, f"N={n} T={tc}")
+
+
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("layout", [0, 1])
 def test_layouts(cx, oracle_lib, engine, layout):
@@ -234,6 +243,22 @@ def test_batch_uneven_arrays(cx, oracle_lib, tile_cfg):
     torch.cuda.synchronize()
     for (n, f, t, lay), x, acc in zip(descs, bufs, accs):
         _compare(acc.cpu().numpy().astype(np.int64), 2 * oracle_lib.xmac(x, n, f, t, lay), n, f"batch N={n}")
+    b.close()
+
+
+def test_batch_small_units_ragged_time(cx, oracle_lib):
+    # the batch's 64-input units take 256-sample chunks: lengths around it
+    import torch
+
+    descs = [(64, 3, 1, 0), (64, 4, 255, 1), (48, 2, 256, 0), (64, 3, 257, 0), (32, 5, 600, 1)]
+    bufs = _batch_inputs(descs)
+    b = cx.Batch(descs, tile_cfg=[cx.CORRX_TILE_UNIT64 | (1 << 8)] * len(descs))
+    accs = b.new_accs()
+    b.zero(accs)
+    b.xmac([torch.from_numpy(x).cuda() for x in bufs], accs)
+    torch.cuda.synchronize()
+    for (n, f, t, lay), x, acc in zip(descs, bufs, accs):
+        _compare(acc.cpu().numpy().astype(np.int64), oracle_lib.xmac(x, n, f, t, lay), n, f"batch N={n} T={t}")
     b.close()
 
 
