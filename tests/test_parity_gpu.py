@@ -129,11 +129,11 @@ def test_accumulates_across_calls(cx, oracle_lib, engine):
              f"{engine} x3")
 
 
-@pytest.mark.parametrize("engine", ENGINES)
-def test_time_split_path(cx, oracle_lib, engine):
+@pytest.mark.parametrize("engine,n", [(e, 256) for e in ENGINES] + [("mfma_i8", 64), ("mfma_i8", 128)])
+def test_time_split_path(cx, oracle_lib, engine, n):
     # few channels and many samples: the library splits time across workgroups
-    n, fc, tc = 256, 1, 20000
-    buf = synth.make_input(5000, n, fc, tc)
+    fc, tc = 1, 20000
+    buf = synth.make_input(5000 + n, n, fc, tc)
     _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} split")
 
 
