@@ -72,16 +72,37 @@ __global__ __launch_bounds__(kThreads) void xmac_plain(Problem p, int ntiles, in
   const int item = tid & 127;
   const int pr = item / 8, oc = item % 8;
 
+  // Eight consecutive inputs of a row as one 8-byte load when the row segment
+  // is whole and aligned; byte loads (bounds-checked) otherwise.
+  const bool aligned8 = p.n_inputs % 8 == 0 && (reinterpret_cast<uintptr_t>(p.in) & 7) == 0;
   for (int tb = t0; tb < t1; tb += 2 * kPairs) {
     {
       const int base = rows ? i0 : j0;
       const int ta = tb + 2 * pr;
+      uint2 w0 = uint2{0, 0}, w1 = uint2{0, 0};
+      if (aligned8 && base + 8 * oc + 8 <= p.n_inputs && ta + 1 < t1) {
+        const uint8_t* r = p.in + row_offset(p, f, ta) + base + 8 * oc;
+        w0 = *reinterpret_cast<const uint2*>(r);
+        w1 = *reinterpret_cast<const uint2*>(r + row_offset(p, f, ta + 1) - row_offset(p, f, ta));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t b0 = load1(p, f, ta, base + 8 * oc + e, t1), b1 = load1(p, f, ta + 1, base + 8 * oc + e, t1);
+          if (e < 4) {
+            w0.x |= b0 << (8 * e);
+            w1.x |= b1 << (8 * e);
+          } else {
+            w0.y |= b0 << (8 * (e - 4));
+            w1.y |= b1 << (8 * (e - 4));
+          }
+        }
+      }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int il = 8 * oc + e;
         int r0, m0, r1, m1;
-        decode1(load1(p, f, ta, base + il, t1), r0, m0);
-        decode1(load1(p, f, ta + 1, base + il, t1), r1, m1);
+        decode1(((e < 4 ? w0.x : w0.y) >> (8 * (e & 3))) & 0xFFu, r0, m0);
+        decode1(((e < 4 ? w1.x : w1.y) >> (8 * (e & 3))) & 0xFFu, r1, m1);
         if (rows) {
           sP[pr][il] = pack4(r0, m0, r1, m1);
           sQ[pr][il] = pack4(m0, -r0, m1, -r1);
