@@ -35,8 +35,9 @@
 //   - registers -> LDS: 4x4 byte transposes (time-major -> input-major), bias,
 //     A-operand bytes [u(t..t+3), w(t..t+3), u(t+4..t+7), w(t+4..t+7)] per
 //     16-byte chunk, XOR swizzled across rows for conflict-free ds_write_b128 /
-//     ds_read_b128; invalid codes only raise a flag, and a rare fix-up pass
-//     over the stage buffer zeroes those samples;
+//     ds_read_b128; an item holding an invalid code has those samples
+//     replaced by the biased zero sample in registers (a branch only such
+//     items take) before it is summed and stored;
 //   - LDS -> MFMA: each wave owns a (NB/2) x (NB/WC) block of G_b in
 //     accumulators (v_mfma_i32_32x32x32_i8); row fragments are read as
 //     A-operands, column fragments are read and converted to B-operands in
@@ -687,8 +688,6 @@ struct StageF8 {
     unpack_phase<2>(ld, y, st, sy, sw, bad, tid);
     unpack_phase<3>(ld, y, st, sy, sw, bad, tid);
   }
-
-  // Invalid samples are zeroed during the unpack: nothing to publish or fix.
 
   // 32 bytes (16 samples) of one input for a K=64 step; `part` = 2 ks + half.
   __device__ static v8i read_frag(const uint8_t* arr, int row, int part) {
