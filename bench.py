@@ -487,7 +487,19 @@ def cpu_baseline(oracle, model, synth, host, n, fc, tc, n_ch):
     return {"value": round(ops / dt / 1e12, 4), "unit": "TOPS", "cores": used, "kind": "oracle",
             "sample": f"{n_ch} of {fc} channels x {tc} samples x {n} inputs (gcc -O2 -fopenmp int64 triple loop, "
                       f"OpenMP over channels), {dt:.1f} s",
+            "cpu": cpu_model(), "host_cpus": os.cpu_count(),
             "xrt": round(model.realtime_factor(tc, dt * fc / n_ch), 4)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":
