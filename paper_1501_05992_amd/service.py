@@ -143,8 +143,8 @@ class Service:
                 a.pending.append((k // obs.chunks_per_integration, self.clock(), token))
             a.next_chunk += 1
             fed = True
-            if not paced and len(a.pending) >= 2:
-                break  # keep at most two integrations queued per observation
+            if len(a.pending) >= 2:
+                break  # at most two integrations in flight: the two host output buffers
         return fed
 
     def _collect(self, a: _Active, keep_outputs: bool) -> bool:
@@ -227,8 +227,9 @@ class GpuBackend:
         rt = type("Runtime", (), {})()
         rt.obs = obs
         rt.corr = corrx.Correlator(obs.n_inputs, obs.n_chan, obs.chunk_samples, corrx.CORRX_LAYOUT_TFI, self.engine)
-        rt.copy = torch.cuda.Stream(device=self.device)
+        rt.copy = torch.cuda.Stream(device=self.device)  # chunks in (host -> device)
         rt.comp = torch.cuda.Stream(device=self.device)
+        rt.d2h = torch.cuda.Stream(device=self.device)   # dumps out, so the next chunks need not wait for them
         nbytes = model.input_bytes(obs.n_inputs, obs.n_chan, obs.chunk_samples)
         rt.stage = [torch.empty(nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
         rt.stage_free = [None, None]
@@ -243,6 +244,7 @@ class GpuBackend:
     def close(self, rt) -> None:
         rt.copy.synchronize()
         rt.comp.synchronize()
+        rt.d2h.synchronize()
         rt.corr.close()
         rt.stage = rt.acc = rt.dump = rt.host = None
 
@@ -271,11 +273,11 @@ class GpuBackend:
         dumped.record(rt.comp)
         out = rt.host[rt.n_out % 2]
         rt.n_out += 1
-        with torch.cuda.stream(rt.copy):
-            rt.copy.wait_event(dumped)
+        with torch.cuda.stream(rt.d2h):
+            rt.d2h.wait_event(dumped)
             out.copy_(rt.dump, non_blocking=True)
             done = torch.cuda.Event()
-            done.record(rt.copy)
+            done.record(rt.d2h)
         rt.dump_free = done
         return (done, out)
 
