@@ -28,6 +28,13 @@
  *     are detected before anything is enqueued.  No C++ exception crosses the ABI.
  *   - A handle is used by one host thread and one stream at a time.  Distinct
  *     handles may be used concurrently on different streams.
+ *   - Calls other than the *_create / *_destroy ones allocate nothing and
+ *     enqueue only kernels on `stream` (no memset, no synchronisation), so they
+ *     may be captured into a HIP graph.  The handle's host-side state (samples
+ *     since corr_zero, whether the accumulator was just zeroed, which selects
+ *     overwrite or add) advances when a call is made, not when a graph replays
+ *     it: capture whole integrations (corr_zero ... corr_dump) so that every
+ *     replay starts from a zeroed accumulator.
  */
 #ifndef CORRX_H
 #define CORRX_H

@@ -335,3 +335,41 @@ def test_binding_rejects_host_short_and_strided_buffers(cx):
     torch.cuda.synchronize()
     assert int(acc.abs().sum()) == 0  # byte 0x00 is the sample 0 + 0j
     c.close()
+
+
+def test_graph_capture_of_a_step(cx, oracle_lib):
+    # zero + xmac + dump captured once and replayed: every replay equals the
+    # eager result, with other device work and synchronisation in between
+    import torch
+
+    n, fc, tc = 128, 6, 700
+    buf = synth.make_input(4242, n, fc, tc)
+    x = torch.from_numpy(buf).cuda()
+    c = cx.Correlator(n, fc, tc)
+    acc = c.new_acc()
+    dst = torch.empty(cx.corr_dump_count(c.h, cx.CORRX_TRI_STATION_POL), dtype=torch.float32, device="cuda")
+    c.zero(acc)
+    c.xmac(x, acc)
+    c.dump(acc, cx.CORRX_TRI_STATION_POL, cx.CORRX_F32, dst)
+    torch.cuda.synchronize()
+    eager = dst.clone()
+    want = oracle_lib.station_pol(oracle_lib.xmac(buf, n, fc, tc), n).astype(np.float32).reshape(-1)
+    assert np.array_equal(eager.cpu().numpy(), want)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            c.zero(acc)
+            c.xmac(x, acc)
+            c.dump(acc, cx.CORRX_TRI_STATION_POL, cx.CORRX_F32, dst)
+    torch.cuda.current_stream().wait_stream(s)
+    for r in range(4):
+        dst.fill_(-1.0)
+        acc.fill_(123)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(dst, eager), f"replay {r}"
+    del g
+    c.close()
