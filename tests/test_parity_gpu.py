@@ -373,3 +373,21 @@ def test_graph_capture_of_a_step(cx, oracle_lib):
         assert torch.equal(dst, eager), f"replay {r}"
     del g
     c.close()
+
+
+_RNG_CASES = np.random.default_rng(1501).integers(0, 2**31, size=16)
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_random_shapes(cx, oracle_lib, case):
+    # seeded random shapes, layouts and engines, element by element
+    rng = np.random.default_rng(int(_RNG_CASES[case]))
+    engine = ["mfma_i8", "plain", "mfma_f8"][case % 3]
+    n = int(rng.integers(1, 257 if engine == "mfma_f8" else 401))
+    fc, tc, layout = int(rng.integers(1, 4)), int(rng.integers(1, 2001)), int(rng.integers(0, 2))
+    print(f"random case {case}: N={n} F={fc} T={tc} layout={layout} {engine}", flush=True)
+    buf = synth.make_input(600 + case, n, fc, tc, layout=layout)
+    if case % 4 == 1:  # some invalid codes
+        buf[rng.integers(0, buf.size, size=max(1, buf.size // 500))] = 0x83
+    _compare(_run(cx, buf, n, fc, tc, layout, engine), oracle_lib.xmac(buf, n, fc, tc, layout), n,
+             f"case {case} N={n} F={fc} T={tc} layout={layout} {engine}")
