@@ -391,3 +391,31 @@ def test_random_shapes(cx, oracle_lib, case):
         buf[rng.integers(0, buf.size, size=max(1, buf.size // 500))] = 0x83
     _compare(_run(cx, buf, n, fc, tc, layout, engine), oracle_lib.xmac(buf, n, fc, tc, layout), n,
              f"case {case} N={n} F={fc} T={tc} layout={layout} {engine}")
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_random_batches(cx, oracle_lib, case):
+    # seeded random uneven batches with random valid tile codes
+    import torch
+
+    rng = np.random.default_rng(7000 + case)
+    descs, codes = [], []
+    for _ in range(int(rng.integers(2, 6))):
+        n = 4 * int(rng.integers(1, 151))
+        descs.append((n, int(rng.integers(1, 5)), int(rng.integers(1, 1501)), int(rng.integers(0, 2))))
+        units = [cx.CORRX_TILE_DEFAULT, cx.CORRX_TILE_UNIT256]
+        if n <= 128:
+            units.append(cx.CORRX_TILE_UNIT128)
+        if n <= 64:
+            units.append(cx.CORRX_TILE_UNIT64)
+        codes.append(int(rng.choice(units)) | (int(rng.choice([0, 1, 2, 4])) << 8))
+    print(f"random batch {case}: {descs} codes {[hex(c) for c in codes]}", flush=True)
+    bufs = [synth.make_input(7100 + 10 * case + k, n, f, t, layout=lay) for k, (n, f, t, lay) in enumerate(descs)]
+    b = cx.Batch(descs, tile_cfg=codes)
+    accs = b.new_accs()
+    b.zero(accs)
+    b.xmac([torch.from_numpy(x).cuda() for x in bufs], accs)
+    torch.cuda.synchronize()
+    for (n, f, t, lay), x, acc in zip(descs, bufs, accs):
+        _compare(acc.cpu().numpy().astype(np.int64), oracle_lib.xmac(x, n, f, t, lay), n, f"batch {case} N={n}")
+    b.close()
