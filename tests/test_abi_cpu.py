@@ -76,3 +76,30 @@ def test_no_gpu_means_edevice(cx):
     assert cx.lib().corr_create(256, 8, 2000, 0, ctypes.byref(h)) == cx.CORRX_EDEVICE
     with pytest.raises(cx.CorrxError):
         cx.corr_create(256, 8, 2000)
+
+
+def test_header_is_plain_c_and_links(cx, tmp_path):
+    # a C99 caller compiles against the header and links the library (not run)
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "caller.c"
+    src.write_text(
+        '#include "corrx.h"\n'
+        "int main(void) {\n"
+        "  corrx_t h = 0;\n"
+        "  void *in = 0, *acc = 0, *vis = 0, *stream = 0;\n"
+        "  if (corr_create(256, 3072, 10000, CORRX_LAYOUT_TFI, &h) != CORRX_OK) return 1;\n"
+        "  corr_zero(h, acc, stream);\n"
+        "  corr_xmac(h, in, acc, stream);\n"
+        "  corr_dump(h, acc, CORRX_TRI_STATION_POL, CORRX_F32, vis, stream);\n"
+        "  return corr_destroy(h) == CORRX_OK && corr_strerror(0) != 0 ? 0 : 1;\n"
+        "}\n")
+    lib_dir = os.path.dirname(cx.LIB_PATH)
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                        "-o", str(tmp_path / "caller"), "-L", lib_dir, "-l:libcorrx.so",
+                        "-Wl,--unresolved-symbols=ignore-in-shared-libs"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
