@@ -36,9 +36,9 @@ KERNEL_SOURCES = ("paper_1501_05992_amd/csrc/xengine_mfma.hip",
                   "paper_1501_05992_amd/csrc/corrx_internal.h",
                   "paper_1501_05992_amd/csrc/api.hip")
 TRAFFIC = {
-    "sources_sha256": "4a24051d0669d8740af134e03d24afbb93927e568e973b88c954022f91654e5a",
-    "read_bytes": 7864060357,   # FETCH_SIZE 3,840,242 KiB x 2.000
-    "write_bytes": 832958218,   # WRITE_SIZE 813,436 KiB x 1.000
+    "sources_sha256": "95067327ca56cc33a6f9f3f92cae43c1eb3db58007bc963b0eca50ce147fa62b",
+    "read_bytes": 7864339724,   # FETCH_SIZE 3,840,199 KiB x 2.000
+    "write_bytes": 848075402,   # WRITE_SIZE 828,199 KiB x 1.000
     "summary": "profiles/xmac_diag_i8_full_band_256x3072x10000_traffic.txt",
 }
 

@@ -397,28 +397,47 @@ __device__ inline void store_tile(int* xa, int col0, const v16i (&acc)[G::FM][G:
 
 // Combine the quadrant of G_b at local rows ib.., columns jb.. (in `own`) with
 // its mirror quadrant (in `mir`; the same area for a diagonal quadrant) and
-// write the lower triangle; local row r is input ibase + r.
+// write the lower triangle; local row r is input ibase + r.  Each thread keeps
+// one column jl and walks the rows jl's wave shares, NT / H rows apart: the
+// column's correction terms are read once, and for H >= 64 the row, its
+// correction terms and its triangle offset are the same in the whole wave
+// (scalar registers); consecutive lanes write consecutive baselines.
 template <class G>
 __device__ inline void combine_quadrant(const Problem& p, int f, int ibase, const int* own, const int* mir, int ib,
                                         int jb, const uint32_t* s_e, const uint32_t* s_g, uint32_t tproc, int mode,
                                         int tid) {
-  constexpr int UN = 8;
+  constexpr int H = G::H, RSTEP = G::NT / H, NPASS = H / RSTEP, UN = NPASS < 8 ? NPASS : 8;
+  static_assert(G::NT % H == 0 && NPASS % UN == 0, "whole passes of whole rows");
+  const bool diag = ib == jb;
+  const int jl = tid % H, lj = jb + jl, j = ibase + lj;
+  int r0 = tid / H;
+  int jwave = 0;  // smallest column of the wave, when the wave shares its rows
+  if constexpr (H >= 64) {
+    r0 = __builtin_amdgcn_readfirstlane(r0);
+    jwave = __builtin_amdgcn_readfirstlane(jl & ~63);
+  }
   const int64_t nb = tri_index(p.n_inputs, 0);
   int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
-  for (int base = tid; base < G::H * G::H; base += G::NT * UN) {
+  const uint32_t cre = 256u * tproc - s_e[lj], gj = s_g[lj];
+  const int* ownp = own + r0 * G::XPITCH + jl;
+  const int* mirp = mir + jl * G::XPITCH + r0;
+#pragma unroll 1
+  for (int k0 = 0; k0 < NPASS; k0 += UN) {
+    // diagonal quadrant: passes whose rows all lie above the wave's columns write nothing
+    if (diag && r0 + RSTEP * (k0 + UN - 1) < jwave) continue;
     int2 val[UN];
     int64_t pos[UN];
     bool ok[UN];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      const int idx = base + u * G::NT;
-      const int il = (idx / G::H) % G::H, jl = idx % G::H;
-      const int li = ib + il, lj = jb + jl;
-      const int i = ibase + li, j = ibase + lj;
-      ok[u] = idx < G::H * G::H && li >= lj && i < p.n_inputs;
-      val[u] = baseline((uint32_t)own[il * G::XPITCH + jl], (uint32_t)mir[jl * G::XPITCH + il], s_e[li], s_e[lj],
-                        s_g[li], s_g[lj], tproc);
-      pos[u] = tri_index(i, j);
+      const int il = r0 + RSTEP * (k0 + u);
+      const int li = ib + il, i = ibase + li;
+      ok[u] = (!diag || il >= jl) && i < p.n_inputs;
+      const uint32_t gij = (uint32_t)ownp[RSTEP * (k0 + u) * G::XPITCH], gji = (uint32_t)mirp[RSTEP * (k0 + u)];
+      // 2 Re = G_b[i][j] + G_b[j][i] - e_i - e_j + 256 T,  2 Im = G_b[j][i] - G_b[i][j] + g_i - g_j
+      val[u] = make_int2((int)(gij + gji - s_e[li] + cre) >> 1, (int)(gji - gij + s_g[li] - gj) >> 1);
+      // n_inputs <= 4096: the offset within the channel fits 32 bits
+      pos[u] = (int64_t)(uint32_t)(((uint32_t)i * (uint32_t)(i + 1) >> 1) + (uint32_t)j);
     }
     write_out<UN>(out, pos, ok, val, mode);
   }
@@ -565,6 +584,14 @@ __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1
   const uint32_t tproc = (uint32_t)(nchunks * 64);
   const int64_t nb = tri_index(p.n_inputs, 0);
   int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
+  // Column terms once per column tile: e_j folded with 256 T, and g_j.
+  uint32_t cre[2], gj[2];
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+    const int lj = 128 + wc * 64 + 32 * z + (lane & 31);  // stage row of j
+    cre[z] = 256u * tproc - s_sy[lj];
+    gj[z] = s_sw[lj];
+  }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -574,16 +601,18 @@ __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1
         int2 val[8];
         int64_t pos[8];
         bool ok[8];
+        const uint32_t j = (uint32_t)(J0 + wc * 64 + 32 * z + (lane & 31));
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr) {
           const int r = 8 * rh + rr;
           const int li = wr * 64 + 32 * x + acc_row(r, lane);  // stage row of i
-          const int lj = 128 + wc * 64 + 32 * z + (lane & 31);  // stage row of j
-          const int i = I0 + li, j = J0 + (lj - 128);
+          const int i = I0 + li;
           ok[rr] = i < p.n_inputs;
-          val[rr] = baseline((uint32_t)c1[x][z][r], (uint32_t)hm[x][z][r], s_sy[li], s_sy[lj], s_sw[li], s_sw[lj],
-                             tproc);
-          pos[rr] = tri_index(i, j);
+          const uint32_t gij = (uint32_t)c1[x][z][r], gji = (uint32_t)hm[x][z][r];
+          // 2 Re = G_b[i][j] + G_b[j][i] - e_i - e_j + 256 T,  2 Im = G_b[j][i] - G_b[i][j] + g_i - g_j
+          val[rr] = make_int2((int)(gij + gji - s_sy[li] + cre[z]) >> 1, (int)(gji - gij + s_sw[li] - gj[z]) >> 1);
+          // n_inputs <= 4096: the offset within the channel fits 32 bits
+          pos[rr] = (int64_t)(((uint32_t)i * (uint32_t)(i + 1) >> 1) + j);
         }
         write_out<8>(out, pos, ok, val, mode);
       }
