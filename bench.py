@@ -36,7 +36,7 @@ KERNEL_SOURCES = ("paper_1501_05992_amd/csrc/xengine_mfma.hip",
                   "paper_1501_05992_amd/csrc/corrx_internal.h",
                   "paper_1501_05992_amd/csrc/api.hip")
 TRAFFIC = {
-    "sources_sha256": "95067327ca56cc33a6f9f3f92cae43c1eb3db58007bc963b0eca50ce147fa62b",
+    "sources_sha256": "aca74408c5cd8001edf96e561744707cd44466e54a6d108f74714b3a57381ba5",
     "read_bytes": 7864339724,   # FETCH_SIZE 3,840,199 KiB x 2.000
     "write_bytes": 848075402,   # WRITE_SIZE 828,199 KiB x 1.000
     "summary": "profiles/xmac_diag_i8_full_band_256x3072x10000_traffic.txt",

@@ -269,15 +269,6 @@ __device__ inline v4i to_b(v4i a) {
 // Row (within a 32x32 tile) held by accumulator register r of this lane.
 __device__ inline int acc_row(int r, int lane) { return ((r >> 2) << 3) + ((lane >> 5) << 2) + (r & 3); }
 
-// Both parts of a baseline from the two biased products (see the header):
-// 2 Re = G_b[i][j] + G_b[j][i] - e_i - e_j + 256 T,  2 Im = G_b[j][i] - G_b[i][j] + g_i - g_j.
-__device__ inline int2 baseline(uint32_t gij, uint32_t gji, uint32_t ei, uint32_t ej, uint32_t gi, uint32_t gj,
-                                uint32_t tproc) {
-  const int re2 = (int)(gij + gji - ei - ej + 256u * tproc);
-  const int im2 = (int)(gji - gij + gi - gj);
-  return make_int2(re2 >> 1, im2 >> 1);
-}
-
 // Write UN baselines per thread with one of the write modes; RMW loads are
 // all issued before any store so their latencies overlap.
 template <int UN>
