@@ -137,6 +137,16 @@ def test_time_split_path(cx, oracle_lib, engine, n):
     _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} split")
 
 
+@pytest.mark.parametrize("n,fc,tc,calls", [(160, 1030, 200, 1), (256, 1024, 130, 2), (131, 1024, 70, 1)])
+def test_many_channels_every_channel(cx, oracle_lib, n, fc, tc, calls):
+    # four or more rounds of units per compute unit, channel counts that do
+    # not divide evenly among them; every channel checked, also on top of an
+    # earlier call (read-modify-write) and for an unaligned input count
+    buf = synth.make_input(5500 + n, n, fc, tc)
+    _compare(_run(cx, buf, n, fc, tc, calls=calls), calls * oracle_lib.xmac(buf, n, fc, tc), n,
+             f"N={n} F={fc} T={tc} x{calls}")
+
+
 def test_single_tone_closed_form(cx):
     n, fc, tc = 256, 2, 1000
     rng = np.random.default_rng(9)
