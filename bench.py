@@ -36,7 +36,7 @@ KERNEL_SOURCES = ("paper_1501_05992_amd/csrc/xengine_mfma.hip",
                   "paper_1501_05992_amd/csrc/corrx_internal.h",
                   "paper_1501_05992_amd/csrc/api.hip")
 TRAFFIC = {
-    "sources_sha256": "aca74408c5cd8001edf96e561744707cd44466e54a6d108f74714b3a57381ba5",
+    "sources_sha256": "c4cbbac5bff3d3ba3eb6856f061a1e99698c46916fb6c7bd89deafba60388408",
     "read_bytes": 7864339724,   # FETCH_SIZE 3,840,199 KiB x 2.000
     "write_bytes": 848075402,   # WRITE_SIZE 828,199 KiB x 1.000
     "summary": "profiles/xmac_diag_i8_full_band_256x3072x10000_traffic.txt",

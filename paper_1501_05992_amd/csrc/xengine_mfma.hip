@@ -491,13 +491,13 @@ __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int
   int* xa = reinterpret_cast<int*>(lds);
   int* xb = xa + G::XAREA;
   constexpr int HW = WC / 2;  // wave columns per quadrant
-  // Round 1: quadrant (1,0) against its mirror (0,1).
+  // Pass 1: quadrant (1,0) against its mirror (0,1).
   if (wr == 0 && wc >= HW) store_tile<G>(xa, (wc - HW) * G::TN, acc, lane);
   if (wr == 1 && wc < HW) store_tile<G>(xb, wc * G::TN, acc, lane);
   __syncthreads();
   combine_quadrant<G>(p, f, ibase, xb, xa, G::H, 0, s_sy, s_sw, tproc, mode, tid);
   __syncthreads();
-  // Round 2: the diagonal quadrants (0,0) and (1,1), each against itself.
+  // Pass 2: the diagonal quadrants (0,0) and (1,1), each against itself.
   if (wr == 0 && wc < HW) store_tile<G>(xa, wc * G::TN, acc, lane);
   if (wr == 1 && wc >= HW) store_tile<G>(xb, (wc - HW) * G::TN, acc, lane);
   __syncthreads();
