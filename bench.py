@@ -71,7 +71,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10, help="untimed steps; the shader clock settles after about five")
     ap.add_argument("--engine", default="mfma_i8")
     ap.add_argument("--n-inputs", type=int, default=256)
     ap.add_argument("--n-chan", type=int, default=3072)
