@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-engine and small-config lines")
     ap.add_argument("--cpu-channels", type=int, default=768, help="channels in the oracle's timed sample")
     ap.add_argument("--check-channels", type=int, default=2, help="channels checked against the oracle")
+    ap.add_argument("--only", choices=("uneven_batch", "coarse_channel"),
+                    help="run only this extra workload (for profiling) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one 1 GiB device-to-device copy (calibrates traffic counters)")
     return ap.parse_args()
@@ -98,6 +100,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.only:
+        import oracle
+
+        fn = {"uneven_batch": lambda: uneven_batch(corrx, model, synth, torch, dev, oracle),
+              "coarse_channel": lambda: coarse_channel(corrx, model, synth, torch, dev)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
     n, fc, tc = args.n_inputs, args.n_chan, args.n_time
     seed = synth.config_seed(2)
     t_start = time.time()
@@ -246,7 +255,19 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
         c.close()
         del acc
         log(f"full band {eng}: {ms:.3f} ms")
-    # one coarse channel: 256 inputs x 128 channels x 5000 samples, int8 MFMA vs plain
+    out.update(coarse_channel(corrx, model, synth, torch, dev))
+    out["uneven_batch"] = uneven_batch(corrx, model, synth, torch, dev, oracle)
+    out["pfb_and_output"] = pfb_and_output(corrx, torch, dev, x, n, fc, tc)
+    out["fine_pfb"] = fine_pfb(corrx, torch, dev, n, fc // 128)
+    out["incoherent_beam"] = incoherent_beam(corrx, synth, torch, dev, oracle, x, host, n, fc, tc)
+    out["streaming"] = streaming(synth, torch)
+    return out
+
+
+def coarse_channel(corrx, model, synth, torch, dev):
+    """One coarse channel, the paper's per-GPU unit: 256 inputs x 128 channels
+    x 5000 samples, int8 MFMA against the plain vector-ALU engine."""
+    out = {}
     n2, f2, t2 = 256, 128, 5000
     h2 = synth.make_input(synth.config_seed(1), n2, f2, t2)
     x2 = torch.from_numpy(h2).to(dev)
@@ -256,14 +277,11 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
         ms = time_xmac(corrx, torch, c, x2, acc, 20)
         ops2 = model.alg_ops(n2, f2, t2)
         out[f"coarse_channel_{eng}"] = {"xmac_ms": round(ms, 4), "tops": round(ops2 / ms / 1e9, 2),
+                                        "frac_of_peak": round(ops2 / ms / 1e9 / PEAK_INT8_TOPS, 4),
                                         "xrt": round(model.realtime_factor(t2, ms * 1e-3), 1)}
+        log(f"coarse channel {eng}: {ms:.4f} ms")
         c.close()
     del x2
-    out["uneven_batch"] = uneven_batch(corrx, model, synth, torch, dev, oracle)
-    out["pfb_and_output"] = pfb_and_output(corrx, torch, dev, x, n, fc, tc)
-    out["fine_pfb"] = fine_pfb(corrx, torch, dev, n, fc // 128)
-    out["incoherent_beam"] = incoherent_beam(corrx, synth, torch, dev, oracle, x, host, n, fc, tc)
-    out["streaming"] = streaming(synth, torch)
     return out
 
 

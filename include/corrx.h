@@ -269,8 +269,11 @@ typedef struct {
 /*
  * Plan a batch of n arrays (1 <= n <= 64) of uneven shapes, run by one
  * persistent launch: one workgroup per compute unit pulls work items (array,
- * channel, tile, time range) from a device queue, longest first.  Each array
- * needs n_inputs % 4 == 0 and 4-byte aligned input (else CORRX_EUNSUPPORTED).
+ * channel, tile, time range) from a device queue, longest first.  The paper's
+ * correlator fixes the number of stations, channels and samples when it is
+ * compiled (Sec. 3.3.3, footnote on compile-time parameters); here every
+ * array of the batch has its own run-time shape.  Each array needs
+ * n_inputs % 4 == 0 and 4-byte aligned input (else CORRX_EUNSUPPORTED).
  * engine: CORRX_ENGINE_MFMA_I8 or AUTO.  Allocates the device work list and
  * the queue counter (freed by corr_batch_destroy).
  * tile_cfg: NULL (built-in choice) or one code per array, chosen by the
@@ -296,7 +299,8 @@ int64_t corr_batch_items(corrx_batch_t b);
 int corr_batch_plan(corrx_batch_t b, int array, int *kind, int *splits);
 
 /*
- * Set every accumulator of the batch to zero (one fill launch per array).  The
+ * Set every accumulator of the batch to zero (one fill launch per array;
+ * Sec. 3.4.3: the accumulation length is the operator's choice).  The
  * next corr_batch_xmac with the same accumulators then writes instead of
  * adding, as corr_xmac does after corr_zero; the caller must not modify them
  * in between.  accs: HOST array of n DEVICE pointers.
@@ -304,11 +308,19 @@ int corr_batch_plan(corrx_batch_t b, int array, int *kind, int *splits);
 int corr_batch_zero(corrx_batch_t b, void *const *accs, void *stream);
 
 /*
- * For every array a: accs[a] += V(ins[a]).  ins and accs are HOST arrays of n
- * DEVICE pointers (same meaning as for corr_xmac, one per array; accs 8-byte
- * aligned).  One persistent launch (plus a one-thread queue reset) on `stream`.
+ * For every array a: accs[a] += V(ins[a]) (Sec. 2 eq. (3), Sec. 3.4, as
+ * corr_xmac).  ins and accs are HOST arrays of n DEVICE pointers (same
+ * meaning as for corr_xmac, one per array; accs 8-byte aligned).  One
+ * persistent launch (plus a one-thread queue reset) on `stream`.  The handle
+ * counts each array's samples since corr_batch_zero; a call that would take
+ * any array past 21,913,098 samples (the int32 bound, |Re|, |Im| <= 98 per
+ * sample) returns CORRX_EOVERFLOW and enqueues nothing.
  */
 int corr_batch_xmac(corrx_batch_t b, const void *const *ins, void *const *accs, void *stream);
+
+/* Samples accumulated for one array of the batch since corr_batch_zero
+ * (host-side count), or a negative status. */
+int64_t corr_batch_samples(corrx_batch_t b, int array);
 
 #ifdef __cplusplus
 }

@@ -52,7 +52,7 @@ SYMBOLS = ("corr_abi_version", "corr_strerror", "corr_create", "corr_destroy", "
            "corr_dump", "corr_dump_avg", "corr_pfb_ingest", "corr_pfb_remap", "corr_fpfb_create",
            "corr_fpfb_destroy", "corr_fpfb_workspace_bytes", "corr_fpfb_tables", "corr_fpfb", "corr_samples",
            "corr_beam", "corr_batch_create", "corr_batch_destroy",
-           "corr_batch_items", "corr_batch_plan", "corr_batch_zero", "corr_batch_xmac")
+           "corr_batch_items", "corr_batch_plan", "corr_batch_zero", "corr_batch_xmac", "corr_batch_samples")
 
 
 class CorrxError(RuntimeError):
@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
             "corr_batch_plan": ([vp, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
             "corr_batch_zero": ([vp, ctypes.POINTER(vp), vp], i),
             "corr_batch_xmac": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp], i),
+            "corr_batch_samples": ([vp, i], i64),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -290,6 +291,10 @@ def corr_batch_xmac(b: int, ins, accs, stream=None) -> None:
     _check(lib().corr_batch_xmac(b, pin, pacc, _stream(stream)), "corr_batch_xmac")
 
 
+def corr_batch_samples(b: int, array: int) -> int:
+    return int(_check(lib().corr_batch_samples(b, array), "corr_batch_samples"))
+
+
 # ---- convenience wrapper --------------------------------------------------------
 
 class Correlator:
@@ -442,6 +447,9 @@ class Batch:
 
     def plan(self, array: int) -> tuple[int, int]:
         return corr_batch_plan(self.h, array)
+
+    def samples(self, array: int) -> int:
+        return corr_batch_samples(self.h, array)
 
     def new_accs(self, device="cuda"):
         return [torch.zeros((f, n * (n + 1) // 2, 2), dtype=torch.int32, device=device)

@@ -22,6 +22,7 @@ struct corrx_batch {
   WorkItem* d_items;
   int* d_counter;
   void* zeroed[kMaxBatch];  // accumulators set to zero by corr_batch_zero and not written since
+  int64_t samples[kMaxBatch];  // samples accumulated per array since corr_batch_zero
 };
 
 namespace {
@@ -215,8 +216,14 @@ int corr_batch_zero(corrx_batch_t b, void* const* accs, void* stream) {
     const int rc = launch_zero(static_cast<int*>(accs[a]), words, reinterpret_cast<hipStream_t>(stream));
     if (rc != CORRX_OK) return rc;
     b->zeroed[a] = accs[a];
+    b->samples[a] = 0;
   }
   return CORRX_OK;
+}
+
+int64_t corr_batch_samples(corrx_batch_t b, int array) {
+  if (!b || array < 0 || array >= b->n) return CORRX_EINVAL;
+  return b->samples[array];
 }
 
 int corr_batch_xmac(corrx_batch_t b, const void* const* ins, void* const* accs, void* stream) {
@@ -235,6 +242,8 @@ int corr_batch_xmac(corrx_batch_t b, const void* const* ins, void* const* accs, 
     p.n_time = b->d[a].n_time;
     p.layout = b->d[a].layout;
     fresh &= b->zeroed[a] == accs[a];
+    // |Re|, |Im| <= 98 per sample: refuse before any int32 accumulator could wrap
+    if (b->samples[a] + b->d[a].n_time > kMaxAccSamples) return CORRX_EOVERFLOW;
   }
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return CORRX_EDEVICE;
@@ -242,6 +251,8 @@ int corr_batch_xmac(corrx_batch_t b, const void* const* ins, void* const* accs, 
   const int rc = launch_batch(args, b->d_items, b->n_items, b->d_counter, b->grid, fresh ? kWriteStore : kWriteAdd,
                               reinterpret_cast<hipStream_t>(stream));
   for (int a = 0; a < b->n; ++a) b->zeroed[a] = nullptr;
+  if (rc == CORRX_OK)
+    for (int a = 0; a < b->n; ++a) b->samples[a] += b->d[a].n_time;
   return rc;
 }
 

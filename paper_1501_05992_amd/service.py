@@ -20,10 +20,18 @@ observations on one GPU:
     free their memory (continuous batching); admitted observations run on
     their own streams, so their kernels overlap on the device;
   - latency of an integration = time its output is back on the host minus the
-    submission time of its last chunk; p50/p99 over all integrations;
+    submission time of its last chunk; p50/p99 over all complete
+    integrations and per observation;
   - real-time factor = input bytes served per second of wall time divided by
     the real-time input rate of the whole mix (every observation streaming at
-    once): 1.0 means the mix is kept up with exactly.
+    once): 1.0 means the mix is kept up with exactly; per observation, its
+    data time over the wall time it was active (admission to last output);
+  - synchronised data only (Sec. 3.3.1): a chunk that has not arrived by its
+    deadline (its release time in paced mode, else the time it was first
+    asked for, plus ``late_s``) marks its integration incomplete.  The
+    integration's remaining chunks are skipped, nothing of it is dumped, and
+    the next integration starts from a zeroed accumulator, so partial data are
+    never merged into a complete one; the result is recorded as incomplete.
 
 The device work goes through a backend (``GpuBackend`` for the HIP library on
 a GPU); the scheduling, admission and statistics are plain Python and can run
@@ -48,7 +56,8 @@ class Observation:
     """One observation: shape, length, and where its chunks come from.
 
     ``chunk(k)`` returns chunk k (samples 500k .. 500k+499) as the backend's
-    host buffer (pinned memory for the GPU backend), layout (t, f, i).
+    host buffer (pinned memory for the GPU backend), layout (t, f, i), or None
+    while the chunk has not arrived yet.
     """
 
     obs_id: str
@@ -76,6 +85,7 @@ class IntegrationResult:
     t_last_chunk: float
     t_done: float
     output: object = None
+    complete: bool = True
 
     @property
     def latency_s(self) -> float:
@@ -90,22 +100,44 @@ class _Active:
     next_chunk: int = 0
     pending: list = field(default_factory=list)  # (integration index, t_last_chunk, token)
     done: int = 0
+    t_asked: float | None = None  # when the service first asked for chunk next_chunk
+
+
+def _percentiles(lat_s: list) -> dict:
+    lat = np.array(lat_s) if lat_s else np.zeros(1)
+    return {"latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "latency_max_ms": float(lat.max() * 1e3)}
 
 
 class Service:
-    """Runs observations to completion; see the module docstring."""
+    """Runs observations to completion; see the module docstring.
 
-    def __init__(self, backend, hbm_budget_bytes: int, clock=time.perf_counter, sleep=time.sleep):
+    ``late_s``: how long after its deadline a chunk is waited for before its
+    integration is declared incomplete.  ``progress``: optional callable given
+    one line of text after every ``progress_every`` results.
+    """
+
+    def __init__(self, backend, hbm_budget_bytes: int, clock=time.perf_counter, sleep=time.sleep,
+                 late_s: float = 0.05, progress=None, progress_every: int = 50):
         self.backend = backend
         self.budget = int(hbm_budget_bytes)
         self.clock = clock
         self.sleep = sleep
+        self.late_s = float(late_s)
+        self.progress = progress
+        self.progress_every = int(progress_every)
+        # integrations whose outputs may be in flight at once (host output buffers per observation)
+        self.max_pending = int(getattr(backend, "host_slots", 2))
         self.queue: list[Observation] = []
         self.active: list[_Active] = []
         self.results: list[IntegrationResult] = []
         self.admit_log: list[tuple[str, float]] = []
         self.in_use = 0
         self.peak_in_use = 0
+        self.peak_pending = 0
+        self._t_admit: dict[str, float] = {}
+        self._t_end: dict[str, float] = {}
 
     def submit(self, obs: Observation) -> None:
         need = self.backend.mem_bytes(obs)
@@ -128,23 +160,48 @@ class Service:
                 self.peak_in_use = max(self.peak_in_use, self.in_use)
                 self.active.append(_Active(obs, rt, now))
                 self.admit_log.append((obs.obs_id, now - t0))
+                self._t_admit[obs.obs_id] = now
+
+    def _drop(self, a: _Active, k: int, now: float) -> None:
+        """Chunk k missed its deadline: its integration is incomplete."""
+        obs = a.obs
+        n_int = k // obs.chunks_per_integration
+        self.results.append(IntegrationResult(obs.obs_id, n_int, now, now, None, complete=False))
+        a.done += 1
+        a.next_chunk = (n_int + 1) * obs.chunks_per_integration
+        a.t_asked = None
 
     def _feed(self, a: _Active, now: float, paced: bool) -> bool:
-        """Submit every chunk of `a` that is due; True if anything was submitted."""
+        """Submit every chunk of `a` that is due; True if anything was submitted or dropped."""
         obs = a.obs
         fed = False
         while a.next_chunk < obs.n_chunks:
             k = a.next_chunk
-            if paced and now < a.t_start + (k + 1) * obs.chunk_period_s:
+            release = a.t_start + (k + 1) * obs.chunk_period_s
+            if paced and now < release:
                 break
             last = (k + 1) % obs.chunks_per_integration == 0
-            token = self.backend.submit_chunk(a.rt, k, obs.chunk(k), last)
+            # An integration's last chunk sends its output to a host buffer:
+            # wait while every buffer still holds an uncollected output.
+            if last and len(a.pending) >= self.max_pending:
+                break
+            data = obs.chunk(k)
+            if data is None:
+                if a.t_asked is None:
+                    a.t_asked = now
+                deadline = (release if paced else a.t_asked) + self.late_s
+                if now < deadline:
+                    break
+                self._drop(a, k, now)
+                fed = True
+                continue
+            token = self.backend.submit_chunk(a.rt, k, data, last)
             if last:
                 a.pending.append((k // obs.chunks_per_integration, self.clock(), token))
+                self.peak_pending = max(self.peak_pending, len(a.pending))
             a.next_chunk += 1
+            a.t_asked = None
             fed = True
-            if len(a.pending) >= 2:
-                break  # at most two integrations in flight: the two host output buffers
         return fed
 
     def _collect(self, a: _Active, keep_outputs: bool) -> bool:
@@ -156,6 +213,9 @@ class Service:
             self.results.append(IntegrationResult(a.obs.obs_id, idx, t_last, t_done, out))
             a.done += 1
             got = True
+            if self.progress and len(self.results) % self.progress_every == 0:
+                self.progress(f"{len(self.results)} integrations done, last {a.obs.obs_id}[{idx}] "
+                              f"{(t_done - t_last) * 1e3:.1f} ms")
         return got
 
     def run(self, paced: bool = True, keep_outputs: bool = False, poll_s: float = 1e-4) -> dict:
@@ -165,6 +225,7 @@ class Service:
         in_bytes = sum(o.n_chunks * model.input_bytes(o.n_inputs, o.n_chan, o.chunk_samples) for o in self.queue)
         rt_rate = sum(model.input_bytes(o.n_inputs, o.n_chan, o.chunk_samples) / o.chunk_period_s
                       for o in self.queue)
+        per_obs = {o.obs_id: o for o in self.queue}
         while self.queue or self.active:
             now = self.clock()
             self._admit(now, t0)
@@ -176,30 +237,47 @@ class Service:
                     self.backend.close(a.rt)
                     self.in_use -= self.backend.mem_bytes(a.obs)
                     self.active.remove(a)
+                    self._t_end[a.obs.obs_id] = self.clock()
                     busy = True
             if not busy:
                 self.sleep(poll_s)
         wall = self.clock() - t0
-        lat = np.array([r.latency_s for r in self.results]) if self.results else np.zeros(1)
-        return {
-            "integrations": len(self.results),
+        complete = [r for r in self.results if r.complete]
+        stats = {
+            "integrations": len(complete),
+            "incomplete": len(self.results) - len(complete),
             "wall_s": wall,
             "data_s_all_observations": data_s,
             "input_bytes": in_bytes,
             "input_gbps": in_bytes / wall / 1e9 if wall > 0 else float("inf"),
             "realtime_input_gbps": rt_rate / 1e9,
             "realtime_factor": in_bytes / wall / rt_rate if wall > 0 else float("inf"),
-            "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "latency_max_ms": float(lat.max() * 1e3),
+            **_percentiles([r.latency_s for r in complete]),
             "peak_hbm_bytes": self.peak_in_use,
+            "peak_pending": self.peak_pending,
             "admissions": list(self.admit_log),
         }
+        obs_stats = {}
+        for oid, o in per_obs.items():
+            rs = [r for r in complete if r.obs_id == oid]
+            active = self._t_end.get(oid, t0) - self._t_admit.get(oid, t0)
+            obs_data = o.n_chunks * o.chunk_period_s
+            obs_stats[oid] = {"integrations": len(rs),
+                              "incomplete": sum(1 for r in self.results if r.obs_id == oid and not r.complete),
+                              "active_s": active, "data_s": obs_data,
+                              "realtime_factor": obs_data / active if active > 0 else float("inf"),
+                              **_percentiles([r.latency_s for r in rs])}
+        stats["per_observation"] = obs_stats
+        return stats
 
 
 class GpuBackend:
     """The HIP library on cuda:0: one Correlator per observation with its own
-    streams, staging slots and output buffers."""
+    streams, staging slots and output buffers.  ``host_slots`` pinned host
+    buffers per observation receive the dumps, so at most that many
+    integrations may await collection at once."""
+
+    host_slots = 2
 
     def __init__(self, engine: str = "mfma_i8", order=None, dtype=None, device: str = "cuda:0"):
         import torch
@@ -236,7 +314,7 @@ class GpuBackend:
         rt.acc = rt.corr.new_acc(self.device)
         tdt = torch.float32 if self.dtype == corrx.CORRX_F32 else torch.int32
         rt.dump = torch.empty(self._dump_count(obs), dtype=tdt, device=self.device)
-        rt.host = [torch.empty(self._dump_count(obs), dtype=tdt, pin_memory=True) for _ in range(2)]
+        rt.host = [torch.empty(self._dump_count(obs), dtype=tdt, pin_memory=True) for _ in range(self.host_slots)]
         rt.dump_free = None
         rt.n_out = 0
         return rt
@@ -271,7 +349,7 @@ class GpuBackend:
         rt.corr.dump(rt.acc, self.order, self.dtype, rt.dump, rt.comp)
         dumped = torch.cuda.Event()
         dumped.record(rt.comp)
-        out = rt.host[rt.n_out % 2]
+        out = rt.host[rt.n_out % self.host_slots]
         rt.n_out += 1
         with torch.cuda.stream(rt.d2h):
             rt.d2h.wait_event(dumped)

@@ -65,6 +65,7 @@ def test_null_handle_calls(cx):
     assert L.corr_acc_bytes(None) == 0
     assert L.corr_destroy(None) == cx.CORRX_OK
     assert L.corr_batch_xmac(None, None, None, None) in (cx.CORRX_EINVAL, cx.CORRX_EUNSUPPORTED)
+    assert L.corr_batch_samples(None, 0) == cx.CORRX_EINVAL
 
 
 def test_no_gpu_means_edevice(cx):

@@ -208,6 +208,31 @@ def test_zero_resets_and_overflow_guard(cx):
     c.close()
 
 
+def test_batch_overflow_guard(cx):
+    """The batch counts samples per array since corr_batch_zero and refuses a
+    call that could wrap an int32 accumulator, before enqueuing anything."""
+    import torch
+
+    descs = [(4, 1, 5_000_000, 0), (8, 2, 1000, 0)]
+    b = cx.Batch(descs)
+    ins = [torch.zeros(n * f * t, dtype=torch.uint8, device="cuda") for (n, f, t, lay) in descs]
+    accs = b.new_accs()
+    b.zero(accs)
+    for k in range(4):
+        b.xmac(ins, accs)
+        assert b.samples(0) == 5_000_000 * (k + 1) and b.samples(1) == 1000 * (k + 1)
+    with pytest.raises(cx.CorrxError) as e:
+        b.xmac(ins, accs)  # 25,000,000 > 21,913,098 samples for array 0
+    assert e.value.status == cx.CORRX_EOVERFLOW
+    assert b.samples(0) == 20_000_000
+    b.zero(accs)
+    assert b.samples(0) == 0 and b.samples(1) == 0
+    b.xmac(ins, accs)
+    torch.cuda.synchronize()
+    assert all(int(a.abs().sum()) == 0 for a in accs)
+    b.close()
+
+
 # 16-lane rows with a 64 x 64 tile transpose (TFI) or direct rows (FTI) when
 # N % 16 == 0; one thread per row otherwise.  Shapes cover whole and ragged
 # tiles, N below, at and above 256, and invalid codes.

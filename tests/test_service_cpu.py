@@ -43,6 +43,8 @@ class FakeBackend:
     def submit_chunk(self, rt, k, host_chunk, last):
         start = max(self.clock(), self.busy_until)
         self.busy_until = start + self.chunk_s
+        if k % rt["obs"].chunks_per_integration == 0:
+            rt["chunks"] = []  # corr_zero opens every integration
         rt["chunks"].append(np.asarray(host_chunk))
         if not last:
             return None
@@ -137,3 +139,145 @@ def test_flat_out_is_faster_than_real_time(oracle_lib):
     st = svc.run(paced=False)
     assert st["realtime_factor"] > 5
     assert st["input_gbps"] == pytest.approx(st["realtime_factor"] * st["realtime_input_gbps"])
+
+
+class SlotBackend(FakeBackend):
+    """Like FakeBackend, but every output lands in one of ``host_slots`` shared
+    host buffers when its copy completes, as the GPU backend's pinned buffers
+    do; ``output`` reads the buffer.  A later output landing in a buffer whose
+    output has not been collected yet would overwrite it."""
+
+    host_slots = 2
+
+    def open(self, obs):
+        rt = super().open(obs)
+        rt.update(slots=[None] * self.host_slots, inflight=[], n_out=0)
+        return rt
+
+    def submit_chunk(self, rt, k, host_chunk, last):
+        tok = super().submit_chunk(rt, k, host_chunk, last)
+        if tok is None:
+            return None
+        slot = rt["n_out"] % self.host_slots
+        rt["n_out"] += 1
+        tok = (tok[0], slot, tok[1])
+        rt["inflight"].append(tok)
+        return tok
+
+    def _land(self, rt):
+        for tok in list(rt["inflight"]):
+            if self.clock() >= tok[0]:
+                rt["slots"][tok[1]] = tok[2]
+                rt["inflight"].remove(tok)
+
+    def done(self, rt, token):
+        self._land(rt)
+        return self.clock() >= token[0]
+
+    def output(self, rt, token):
+        self._land(rt)
+        return rt["slots"][token[1]].copy()
+
+
+def _expected(oracle_lib, obs_data, n, f, period, n_int):
+    per = n * f * period * 10
+    return [oracle_lib.xmac(obs_data[k * per:(k + 1) * per], n, f, period * 10) for k in range(n_int)]
+
+
+def test_outputs_wait_for_free_host_buffers(oracle_lib):
+    """Slow output copies (the device lags the host): the service never has
+    more integrations awaiting collection than host buffers, and every
+    collected output is its own integration's."""
+    clock = FakeClock()
+    be = SlotBackend(clock, oracle_lib, chunk_s=0.0005, dump_s=0.05)
+    period, n, f, n_int = 100, 8, 2, 6
+    data = synth.make_input(11, n, f, period * 10 * n_int, threads=1)
+    per = n * f * period
+    obs = Observation("a", n, f, n_int, lambda k: data[k * per:(k + 1) * per], chunk_samples=period)
+    svc = Service(be, 10 ** 9, clock=clock, sleep=clock.sleep)
+    svc.submit(obs)
+    st = svc.run(paced=False, keep_outputs=True)
+    assert st["integrations"] == n_int and st["incomplete"] == 0
+    assert 1 <= st["peak_pending"] <= be.host_slots
+    want = _expected(oracle_lib, data, n, f, period, n_int)
+    got = {r.index: r.output for r in svc.results}
+    for k in range(n_int):
+        assert np.array_equal(got[k], want[k]), k
+
+
+def _late_obs(data, n, f, period, n_int, clock, arrival):
+    """Chunk k arrives at clock time arrival(k) (inf: never)."""
+    per = n * f * period
+
+    def chunk(k):
+        return data[k * per:(k + 1) * per] if clock() >= arrival(k) else None
+
+    return Observation("late", n, f, n_int, chunk, chunk_samples=period)
+
+
+@pytest.mark.parametrize("paced", [True, False])
+def test_missing_chunk_drops_its_integration(oracle_lib, paced):
+    """A chunk that never arrives: its integration is recorded incomplete with
+    no output, nothing of it leaks into the next integration, and the others
+    are correct (Sec. 3.3.1: only synchronised data are correlated)."""
+    clock = FakeClock()
+    be = SlotBackend(clock, oracle_lib)
+    period, n, f, n_int = 100, 8, 2, 4
+    data = synth.make_input(12, n, f, period * 10 * n_int, threads=1)
+    missing = 13  # integration 1, chunk 3
+    obs = _late_obs(data, n, f, period, n_int, clock, lambda k: float("inf") if k == missing else 0.0)
+    svc = Service(be, 10 ** 9, clock=clock, sleep=clock.sleep, late_s=0.02)
+    svc.submit(obs)
+    st = svc.run(paced=paced, keep_outputs=True)
+    assert st["integrations"] == 3 and st["incomplete"] == 1
+    assert st["per_observation"]["late"]["incomplete"] == 1
+    want = _expected(oracle_lib, data, n, f, period, n_int)
+    by = {r.index: r for r in svc.results}
+    assert not by[1].complete and by[1].output is None
+    for k in (0, 2, 3):
+        assert by[k].complete and np.array_equal(by[k].output, want[k]), k
+    # the incomplete integration was declared no earlier than the chunk's deadline
+    if paced:
+        release = (missing + 1) * obs.chunk_period_s
+        assert by[1].t_done >= release + 0.02 - 1e-9
+
+
+def test_late_chunk_within_deadline_is_used_after_it_is_dropped(oracle_lib):
+    """Paced: a chunk arriving 10 ms after its release is waited for (late_s =
+    30 ms); one arriving 100 ms late is not, and its integration is dropped
+    even though the data turn up afterwards."""
+    clock = FakeClock()
+    be = SlotBackend(clock, oracle_lib)
+    period, n, f, n_int = 100, 8, 2, 3
+    data = synth.make_input(13, n, f, period * 10 * n_int, threads=1)
+    p = period / model.SAMPLE_RATE_HZ
+    late = {4: 0.010, 25: 0.100}  # chunk -> delay after its release time
+    obs = _late_obs(data, n, f, period, n_int, clock, lambda k: (k + 1) * p + late.get(k, 0.0))
+    svc = Service(be, 10 ** 9, clock=clock, sleep=clock.sleep, late_s=0.030)
+    svc.submit(obs)
+    st = svc.run(paced=True, keep_outputs=True)
+    by = {r.index: r for r in svc.results}
+    want = _expected(oracle_lib, data, n, f, period, n_int)
+    assert by[0].complete and np.array_equal(by[0].output, want[0])
+    assert by[1].complete and np.array_equal(by[1].output, want[1])
+    assert not by[2].complete
+    assert st["integrations"] == 2 and st["incomplete"] == 1
+
+
+def test_per_observation_statistics(oracle_lib):
+    clock = FakeClock()
+    be = FakeBackend(clock, oracle_lib)
+    obs = [_obs("a", 8, 2, 3, 21), _obs("b", 8, 4, 2, 22, arrival=0.01)]
+    svc = Service(be, 10 ** 9, clock=clock, sleep=clock.sleep)
+    for o in obs:
+        svc.submit(o)
+    st = svc.run(paced=True)
+    per = st["per_observation"]
+    assert set(per) == {"a", "b"}
+    assert per["a"]["integrations"] == 3 and per["b"]["integrations"] == 2
+    for o in obs:
+        s = per[o.obs_id]
+        assert s["data_s"] == pytest.approx(o.n_chunks * o.chunk_period_s)
+        # paced: an observation cannot be served faster than its data arrive
+        assert 0.5 < s["realtime_factor"] <= 1.0 + 1e-6
+        assert s["latency_p99_ms"] >= s["latency_p50_ms"] > 0
