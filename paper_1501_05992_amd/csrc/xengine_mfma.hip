@@ -19,11 +19,12 @@
 //
 // Work units.  A channel's N x N square of G_b is tiled by blocks of 256
 // inputs.  A diagonal unit computes one diagonal block (NB = 64, 128 or 256
-// inputs) in full and pairs each element with its transpose through LDS.  A
-// pair unit takes 128 rows I of an off-diagonal block and the 256 columns J
-// and computes both G_b[I][J] = A_I B_J^T and G_b[J][I]^T = B_I A_J^T, so the
-// two halves of every baseline meet in registers.  Units run as standalone
-// grids (one launch per unit kind) or inside the persistent batch kernel.
+// inputs) in full and pairs each element with its transpose through LDS.  The
+// off-diagonal blocks use the direct complex form instead (two real products
+// per baseline that share the column operand, no transpose): a cross unit
+// takes 128 rows I of an off-diagonal block and its 256 columns J.  Units run
+// as standalone grids (one launch per unit kind) or inside the persistent
+// batch kernel.
 //
 // Unit structure (one workgroup = one unit x one time range, 8 waves for the
 // 256-input units, two waves per SIMD so that one wave's vector-ALU and LDS
@@ -55,8 +56,11 @@ namespace corrx {
 
 // ROWS inputs staged per chunk of TC samples by NT threads.  Stage row r holds
 // the A-operand bytes of one input: 16-byte chunk k = samples 8k..8k+7 as
-// [u(4), w(4), u(4), w(4)], chunks XOR-swizzled per row.
-template <int ROWS, int TC, int NT>
+// [u(4), w(4), u(4), w(4)], chunks XOR-swizzled per row.  SCALAR_RSRC: read
+// the load descriptors from the first lane (for units whose block indices the
+// compiler cannot prove uniform; a descriptor in vector registers costs a loop
+// per load).
+template <int ROWS, int TC, int NT, bool SCALAR_RSRC = false>
 struct Stage {
   static constexpr int QUADS = ROWS / 4;
   static constexpr int GROUPS = TC / 8;              // 8-row groups per chunk
@@ -119,9 +123,17 @@ struct Stage {
       }
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const int nr = max(nrec0 - r * stride32, 0);
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<uint8_t*>(base + (int64_t)r * stride), (short)0, nr, kBufferRsrcWord3);
+        int nr = max(nrec0 - r * stride32, 0);
+        const uint8_t* rb = base + (int64_t)r * stride;
+        if constexpr (SCALAR_RSRC) {
+          nr = __builtin_amdgcn_readfirstlane(nr);
+          const uint64_t a = reinterpret_cast<uint64_t>(rb);
+          rb = reinterpret_cast<const uint8_t*>(
+              ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) << 32) |
+              (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a));
+        }
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(rb), (short)0, nr, kBufferRsrcWord3);
 #pragma unroll
         for (int k = 0; k < ITER; ++k) ld[k][r] = __builtin_amdgcn_raw_buffer_load_b32(rs, off[k], 0, 0);
       }
@@ -234,7 +246,12 @@ struct Stage {
   }
 
   // Reduce the per-thread sums into s_sy / s_sw, then turn them into the
-  // correction terms e_k = Sy_k + 30 Sw_k and g_k = Sy_k - 2 Sw_k in place.
+  // correction terms in place: for the single-GEMM form (CROSS false)
+  // e_k = Sy_k + 30 Sw_k and g_k = Sy_k - 2 Sw_k; for the direct complex form
+  // (CROSS true) 8 (Su_k + Sw_k) = (Sy_k + 15 Sw_k) / 2 and
+  // 8 (Sw_k - Su_k) = (17 Sw_k - Sy_k) / 2, with Sy = 16 Su + Sw (both
+  // numerators are even).
+  template <bool CROSS = false>
   __device__ static void finish_sums(const uint32_t (&sy)[SUMS][4], const uint32_t (&sw)[SUMS][4], uint32_t* s_sy,
                                      uint32_t* s_sw, int tid) {
 #pragma unroll
@@ -250,8 +267,13 @@ struct Stage {
     __syncthreads();
     for (int k = tid; k < ROWS; k += NT) {
       const uint32_t y = s_sy[k], w = s_sw[k];
-      s_sy[k] = y + 30u * w;
-      s_sw[k] = y - 2u * w;
+      if constexpr (CROSS) {
+        s_sy[k] = (y + 15u * w) >> 1;  // non-negative
+        s_sw[k] = (uint32_t)((int32_t)(17u * w - y) >> 1);  // of either sign: arithmetic shift
+      } else {
+        s_sy[k] = y + 30u * w;
+        s_sw[k] = y - 2u * w;
+      }
     }
     __syncthreads();
   }
@@ -506,40 +528,53 @@ __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int
   __syncthreads();
 }
 
-// ---- pair unit ----------------------------------------------------------------
-
-// Rows I0 .. I0+127 against columns J0 .. J0+255 (all j < i), 8 waves as 2 x 4
-// tiles of 64 x 64, each holding both products (C1 = A_I B_J^T, Hm = B_I A_J^T).
-struct PairGeom {
+// ---- cross unit ---------------------------------------------------------------
+//
+// Rows I0 .. I0+127 against columns J0 .. J0+255 of an off-diagonal block
+// pair (every row input above every column input), in the direct complex
+// form rather than the single biased GEMM: with the staged bytes
+// P_k = (u_k, w_k) of every input and Q_i = (w_i, 16 - u_i) formed from a row
+// fragment in registers (two subtractions per 16 bytes; the swap is free),
+//     R_ij = P_i . P_j = Re V_ij + 8 S_i + 8 S_j - 128 T
+//     M_ij = Q_i . P_j = Im V_ij + 8 D_i + 8 S_j
+// with S_k = Su_k + Sw_k and D_k = Sw_k - Su_k (sums of u and w over the T
+// processed samples).  Both products share the column operand, so a K-step
+// reads four fragments for eight MFMAs and converts only the two row ones.
+// 8 waves as 2 x 4 tiles of 64 x 64 baselines, each holding R and M.
+struct CrossGeom {
   static constexpr int NT = 512;
   static constexpr int ROWS = 384;                   // stage rows: 128 of I, then 256 of J
   static constexpr int LDS = 2 * ROWS * 128;
 };
 
+__device__ inline v4i to_q(v4i a) {
+  return v4i{a.y, (int)(0x10101010u - (uint32_t)a.x), a.w, (int)(0x10101010u - (uint32_t)a.z)};
+}
+
 template <bool ALIGNED>
-__device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1, int tid, uint8_t* lds,
-                         uint32_t* s_sy, uint32_t* s_sw, int mode) {
+__device__ void run_cross(const Problem& p, int f, int I0, int J0, int t0, int t1, int tid, uint8_t* lds,
+                          uint32_t* s_sy, uint32_t* s_sw, int mode) {
   // Values derived from the thread index are recomputed for every unit: when
   // units run in a loop (the persistent kernel), hoisting them out of it would
   // keep them live across the whole unit and exhaust the registers.
   asm volatile("" : "+v"(tid));
-  using S = Stage<PairGeom::ROWS, 64, PairGeom::NT>;
+  using S = Stage<CrossGeom::ROWS, 64, CrossGeom::NT, true>;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave / 4, wc = wave % 4;
   const int nchunks = t1 > t0 ? (t1 - t0 + 63) / 64 : 0;
   const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
 
-  for (int k = tid; k < PairGeom::ROWS; k += PairGeom::NT) {
+  for (int k = tid; k < CrossGeom::ROWS; k += CrossGeom::NT) {
     s_sy[k] = 0;
     s_sw[k] = 0;
   }
   __syncthreads();
 
-  v16i c1[2][2], hm[2][2];
+  v16i re[2][2], im[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int z = 0; z < 2; ++z) c1[x][z] = hm[x][z] = v16i{0};
+    for (int z = 0; z < 2; ++z) re[x][z] = im[x][z] = v16i{0};
   uint32_t sy[S::SUMS][4], sw[S::SUMS][4];
 #pragma unroll
   for (int k = 0; k < S::SUMS; ++k)
@@ -551,37 +586,34 @@ __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1
   const typename S::Map m{I0, 32, J0};
   run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, sy, sw, nchunks,
                          [&](const uint8_t* st, int ks) {
-                           v4i ai[2], bi[2], aj[2], bj[2];
+                           v4i a[2], q[2], b[2];
 #pragma unroll
                            for (int x = 0; x < 2; ++x) {
-                             ai[x] = S::read_frag(st, irow + 32 * x, 2 * ks + half);
-                             aj[x] = S::read_frag(st, jrow + 32 * x, 2 * ks + half);
+                             a[x] = S::read_frag(st, irow + 32 * x, 2 * ks + half);
+                             b[x] = S::read_frag(st, jrow + 32 * x, 2 * ks + half);
                            }
 #pragma unroll
-                           for (int x = 0; x < 2; ++x) {
-                             bi[x] = to_b(ai[x]);
-                             bj[x] = to_b(aj[x]);
-                           }
+                           for (int x = 0; x < 2; ++x) q[x] = to_q(a[x]);
 #pragma unroll
                            for (int x = 0; x < 2; ++x)
 #pragma unroll
                              for (int z = 0; z < 2; ++z) {
-                               c1[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai[x], bj[z], c1[x][z], 0, 0, 0);
-                               hm[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bi[x], aj[z], hm[x][z], 0, 0, 0);
+                               re[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[x], b[z], re[x][z], 0, 0, 0);
+                               im[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(q[x], b[z], im[x][z], 0, 0, 0);
                              }
                          });
 
-  S::finish_sums(sy, sw, s_sy, s_sw, tid);
+  S::template finish_sums<true>(sy, sw, s_sy, s_sw, tid);
   const uint32_t tproc = (uint32_t)(nchunks * 64);
   const int64_t nb = tri_index(p.n_inputs, 0);
   int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
-  // Column terms once per column tile: e_j folded with 256 T, and g_j.
-  uint32_t cre[2], gj[2];
+  // Column terms once per column tile: 128 T - 8 S_j for Re, 8 S_j for Im.
+  uint32_t cre[2], cim[2];
 #pragma unroll
   for (int z = 0; z < 2; ++z) {
     const int lj = 128 + wc * 64 + 32 * z + (lane & 31);  // stage row of j
-    cre[z] = 256u * tproc - s_sy[lj];
-    gj[z] = s_sw[lj];
+    cre[z] = 128u * tproc - s_sy[lj];
+    cim[z] = s_sy[lj];
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -599,9 +631,9 @@ __device__ void run_pair(const Problem& p, int f, int I0, int J0, int t0, int t1
           const int li = wr * 64 + 32 * x + acc_row(r, lane);  // stage row of i
           const int i = I0 + li;
           ok[rr] = i < p.n_inputs;
-          const uint32_t gij = (uint32_t)c1[x][z][r], gji = (uint32_t)hm[x][z][r];
-          // 2 Re = G_b[i][j] + G_b[j][i] - e_i - e_j + 256 T,  2 Im = G_b[j][i] - G_b[i][j] + g_i - g_j
-          val[rr] = make_int2((int)(gij + gji - s_sy[li] + cre[z]) >> 1, (int)(gji - gij + s_sw[li] - gj[z]) >> 1);
+          // Re V = R - 8 S_i - 8 S_j + 128 T,  Im V = M - 8 D_i - 8 S_j
+          val[rr] = make_int2((int)((uint32_t)re[x][z][r] - s_sy[li] + cre[z]),
+                              (int)((uint32_t)im[x][z][r] - s_sw[li] - cim[z]));
           // n_inputs <= 4096: the offset within the channel fits 32 bits
           pos[rr] = (int64_t)(((uint32_t)i * (uint32_t)(i + 1) >> 1) + j);
         }
@@ -822,7 +854,7 @@ __global__ __launch_bounds__(128 * WC, unit_min_blocks<128 * WC>) void xmac_diag
                             nsplit > 1 ? (int)kWriteAtomic : mode);
 }
 
-// Pair units: unit id -> (channel, (block pair, half), time split).
+// Cross units: unit id -> (channel, (block pair, half), time split).
 __device__ inline void pair_decode(int pu, int& I0, int& J0) {
   const int half = pu & 1, pr = pu >> 1;  // pr -> (bi, bj), bi > bj, row-major
   int bi = (int)((sqrtf(8.0f * pr + 1.0f) + 1.0f) * 0.5f);
@@ -834,9 +866,9 @@ __device__ inline void pair_decode(int pu, int& I0, int& J0) {
 }
 
 template <bool ALIGNED>
-__global__ __launch_bounds__(512, 1) void xmac_pair_i8(Problem p, int npair, int nsplit, int tsplit, int mode) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[PairGeom::LDS];
-  __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS];
+__global__ __launch_bounds__(512, 1) void xmac_cross_i8(Problem p, int npair, int nsplit, int tsplit, int mode) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[CrossGeom::LDS];
+  __shared__ uint32_t s_sy[CrossGeom::ROWS], s_sw[CrossGeom::ROWS];
   int u = xcd_remap(blockIdx.x, gridDim.x);
   const int sp = u % nsplit;
   u /= nsplit;
@@ -844,7 +876,7 @@ __global__ __launch_bounds__(512, 1) void xmac_pair_i8(Problem p, int npair, int
   int I0, J0;
   pair_decode(pu, I0, J0);
   const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
-  run_pair<ALIGNED>(p, f, I0, J0, t0, t1, threadIdx.x, lds, s_sy, s_sw, nsplit > 1 ? (int)kWriteAtomic : mode);
+  run_cross<ALIGNED>(p, f, I0, J0, t0, t1, threadIdx.x, lds, s_sy, s_sw, nsplit > 1 ? (int)kWriteAtomic : mode);
 }
 
 template <bool ALIGNED>
@@ -879,16 +911,16 @@ static int launch_diag(const Problem& p, int nblk, int nsplit, int mode, hipStre
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
-static int launch_pair(const Problem& p, int npair, int nsplit, int mode, hipStream_t s) {
+static int launch_cross(const Problem& p, int npair, int nsplit, int mode, hipStream_t s) {
   const int tsplit = (p.n_time + nsplit - 1) / nsplit;
   const int64_t grid = (int64_t)p.n_chan * npair * nsplit;
   if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
   if (aligned_problem(p))
-    hipLaunchKernelGGL((xmac_pair_i8<true>), dim3((unsigned)grid), dim3(PairGeom::NT), 0, s, p, npair, nsplit, tsplit,
-                       mode);
+    hipLaunchKernelGGL((xmac_cross_i8<true>), dim3((unsigned)grid), dim3(CrossGeom::NT), 0, s, p, npair, nsplit,
+                       tsplit, mode);
   else
-    hipLaunchKernelGGL((xmac_pair_i8<false>), dim3((unsigned)grid), dim3(PairGeom::NT), 0, s, p, npair, nsplit, tsplit,
-                       mode);
+    hipLaunchKernelGGL((xmac_cross_i8<false>), dim3((unsigned)grid), dim3(CrossGeom::NT), 0, s, p, npair, nsplit,
+                       tsplit, mode);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
@@ -919,14 +951,14 @@ int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg
   if (p.n_inputs <= 128) return launch_diag<128, 2>(p, 1, nsplit, mode, s);
   const int nb = (p.n_inputs + 255) / 256;
   int rc = launch_diag<256, 4>(p, nb, nsplit, mode, s);
-  if (rc == CORRX_OK && nb > 1) rc = launch_pair(p, nb * (nb - 1), nsplit, mode, s);
+  if (rc == CORRX_OK && nb > 1) rc = launch_cross(p, nb * (nb - 1), nsplit, mode, s);
   return rc;
 }
 
 // ---- persistent batch kernel ----------------------------------------------------
 
 constexpr int kBatchLds =
-    DiagGeom<256, 4>::LDS > PairGeom::LDS ? DiagGeom<256, 4>::LDS : PairGeom::LDS;
+    DiagGeom<256, 4>::LDS > CrossGeom::LDS ? DiagGeom<256, 4>::LDS : CrossGeom::LDS;
 // The batch's 64-input units take 256-sample chunks: with only two units per
 // compute unit (one workgroup of 512 threads), the longer chunks keep four
 // times as many input bytes in flight per unit as 64-sample chunks.
@@ -980,13 +1012,32 @@ __device__ __noinline__ int batch_small_run(const Problem* table, const WorkItem
   return it;
 }
 
+// The two 256-input unit kinds of the batch, each out of line with its own
+// register allocation (inlined side by side in the persistent loop they would
+// have to share one, and spill).
+__device__ __noinline__ void batch_diag256(const Problem* table, WorkItem w, int base_mode, uint8_t* lds,
+                                           uint32_t* s_sy, uint32_t* s_sw) {
+  const Problem p = table[w.array];
+  const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
+  run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
+}
+
+__device__ __noinline__ void batch_cross(const Problem* table, WorkItem w, int base_mode, uint8_t* lds,
+                                         uint32_t* s_sy, uint32_t* s_sw) {
+  const Problem p = table[w.array];
+  const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
+  int I0, J0;
+  pair_decode(w.tile, I0, J0);
+  run_cross<true>(p, w.channel, I0, J0, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
+}
+
 // One workgroup per compute unit pulls work items from a device counter until
 // the list is exhausted.  Every item is one unit (or two small units side by
 // side, on channels f and f+1 of the same array).  All arrays must be aligned.
 __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const WorkItem* items, int n_items,
                                                          int* counter, int base_mode) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kBatchLds];
-  __shared__ uint32_t s_sy[PairGeom::ROWS], s_sw[PairGeom::ROWS];
+  __shared__ uint32_t s_sy[CrossGeom::ROWS], s_sw[CrossGeom::ROWS];
   __shared__ int s_item;
   const int tid = threadIdx.x;
   // The problem table is the first kernel argument: read it in place in the
@@ -1005,15 +1056,10 @@ __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const Wo
       it = batch_small_run<128>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
       continue;
     }
-    const Problem p = table[w.array];
-    const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
-    if (w.kind == kUnitDiag256) {
-      run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, tid, lds, s_sy, s_sw, mode);
-    } else {
-      int I0, J0;
-      pair_decode(w.tile, I0, J0);
-      run_pair<true>(p, w.channel, I0, J0, w.t0, w.t1, tid, lds, s_sy, s_sw, mode);
-    }
+    if (w.kind == kUnitDiag256)
+      batch_diag256(table, w, base_mode, lds, s_sy, s_sw);
+    else
+      batch_cross(table, w, base_mode, lds, s_sy, s_sw);
     it = batch_fetch(counter, &s_item);
   }
 }

@@ -3,7 +3,8 @@ configuration, on sampled channels that the CPU oracle computes one by one
 (tolerance 0: integer sums).
 
 - full band: 256 inputs x 3072 channels x 10000 samples, TFI, for all three
-  engines, plus the station/polarisation float32 dump of the timed step;
+  engines, every channel for the int8 engine, plus the station/polarisation
+  float32 dump of the timed step;
 - one coarse channel: 256 x 128 x 5000, MFMA and plain;
 - the uneven batch: 64/256/512/2048 inputs in one persistent launch;
 - the four streaming observations at full channel counts, served together
@@ -90,6 +91,24 @@ def test_full_band_sampled_channels(cx, full_band, engine):
     c, acc = _check_sampled(cx, full_band, engine)
     del acc
     c.close()
+
+
+def test_full_band_every_channel(cx, oracle_lib, full_band):
+    """The int8 engine on the whole full band, every one of the 3072 channels
+    against the oracle (about a minute of oracle time on the host's cores),
+    compared in blocks of 768 channels."""
+    c, acc = _check_sampled(cx, full_band, "mfma_i8")
+    got = acc.cpu().numpy()
+    del acc
+    c.close()
+    n, fc, tc = full_band.n, full_band.fc, full_band.tc
+    tfi = full_band.host.reshape(tc, fc, n)
+    for f0 in range(0, fc, 768):
+        f1 = min(fc, f0 + 768)
+        sub = np.ascontiguousarray(tfi[:, f0:f1, :]).reshape(-1)
+        want = oracle_lib.xmac(sub, n, f1 - f0, tc)
+        assert np.array_equal(got[f0:f1].astype(np.int64), want), f"channels {f0}..{f1 - 1} differ"
+        print(f"channels {f0}..{f1 - 1} equal the oracle", flush=True)
 
 
 def test_full_band_step_dump(cx, oracle_lib, full_band):

@@ -67,9 +67,9 @@ def test_input_counts(cx, oracle_lib, engine, n):
 
 
 @pytest.mark.parametrize("engine", ENGINES_ANY_N)
-@pytest.mark.parametrize("n", [257, 300, 384, 511, 512, 513, 700, 1024])
+@pytest.mark.parametrize("n", [257, 300, 384, 511, 512, 513, 700, 1024, 2048])
 def test_multi_block_input_counts(cx, oracle_lib, engine, n):
-    # more than 256 inputs: diagonal blocks plus pair units
+    # more than 256 inputs: diagonal blocks plus cross units
     fc, tc = 2, 77
     buf = synth.make_input(8000 + n, n, fc, tc)
     _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} N={n}")
@@ -119,6 +119,21 @@ def test_invalid_codes_and_extreme_values(cx, oracle_lib, engine, n):
     buf[n * 40: n * 80] = 0x99
     buf[n * 80: n * 90] = 0x79
     _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} bytes")
+
+
+@pytest.mark.parametrize("engine", ENGINES_ANY_N)
+@pytest.mark.parametrize("n", [300, 520])
+def test_invalid_codes_and_extreme_values_large_arrays(cx, oracle_lib, engine, n):
+    # the same byte mix through the cross units (rows and columns of
+    # off-diagonal blocks), with a ragged last block
+    fc, tc = 2, 200
+    rng = np.random.default_rng(n)
+    buf = rng.integers(0, 256, size=n * fc * tc, dtype=np.uint8)
+    buf[: n * 30] = 0x77
+    buf[n * 30: n * 60] = 0x99
+    buf[n * 60: n * 70] = 0x79
+    buf[n * 70: n * 80] = 0x97
+    _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} bytes N={n}")
 
 
 @pytest.mark.parametrize("engine", ENGINES)
