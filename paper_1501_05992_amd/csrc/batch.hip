@@ -164,10 +164,14 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
           items.push_back(w);
         }
   }
-  // Longest first: the dynamic queue then balances the tail.
+  // Longest first: the dynamic queue then balances the tail.  Items of equal
+  // cost are grouped by kind, so that a workgroup mostly meets runs of one
+  // kind (the kernel switches kinds through an out-of-line call).
   std::stable_sort(items.begin(), items.end(), [&](const WorkItem& x, const WorkItem& y) {
-    return item_cost(x.kind, b->d[x.array].n_inputs, x.t1 - x.t0) >
-           item_cost(y.kind, b->d[y.array].n_inputs, y.t1 - y.t0);
+    const double cx = item_cost(x.kind, b->d[x.array].n_inputs, x.t1 - x.t0);
+    const double cy = item_cost(y.kind, b->d[y.array].n_inputs, y.t1 - y.t0);
+    if (cx != cy) return cx > cy;
+    return x.kind < y.kind;
   });
   if (items.size() > 0x7FFFFFFF) {
     delete b;

@@ -77,6 +77,20 @@ __device__ inline uint32_t invalid_flags(uint32_t y) {
   return (y - 0x11111111u) & ~y & 0x88888888u;
 }
 
+// The same test on the raw (unbiased) word x, before masking with 0x88888888:
+// bit 3 of ~y equals bit 3 of x, and y - 0x11111111 = (x ^ 0x88888888) +
+// 0xEEEEEEEF.  k is 0xEEEEEEEF held in a vector register (see vconst): a VOP3
+// instruction on this target reads at most one scalar operand, and with the
+// second constant in a vector register the compiler forms one v_xad_u32.
+__device__ inline uint32_t invalid_flags_raw(uint32_t x, uint32_t k) { return ((x ^ 0x88888888u) + k) & x; }
+
+// A constant the compiler must hold in a vector register: the empty asm
+// statement emits no instruction, it only hides the value.
+__device__ inline uint32_t vconst(uint32_t c) {
+  asm volatile("" : "+v"(c));
+  return c;
+}
+
 // Replace every byte of y that has a zero nibble by 0x88 (a valid 0 + 0j):
 // an invalid sample contributes nothing.
 __device__ inline uint32_t mask_invalid(uint32_t y) {
@@ -87,16 +101,31 @@ __device__ inline uint32_t mask_invalid(uint32_t y) {
   return (y & m) | (0x88888888u & ~m);
 }
 
-// Biased real / imaginary parts (0..15) of four samples, one per byte.
+// The same on raw words: with y = x ^ 0x88888888, y & 0x77777777 =
+// x & 0x77777777 and bit 3 of y is bit 3 of ~x; the masked sample returns to
+// raw 0x00, so the result is x with every invalid byte cleared.
+__device__ inline uint32_t mask_invalid_raw(uint32_t x) {
+  const uint32_t nz = (((x & 0x77777777u) + 0x77777777u) | ~x) & 0x88888888u;  // bit 3 per nonzero nibble of y
+  const uint32_t both = nz & (nz >> 4) & 0x08080808u;                           // bit 3 per valid byte
+  const uint32_t one = both >> 3;                                               // 0x01 per valid byte
+  return x & ((one << 8) - one);                                                // 0xFF per valid byte
+}
+
+// Biased real / imaginary parts (0..15) of four samples, one per byte, from
+// biased words y ...
 __device__ inline uint32_t bre4(uint32_t y) { return (y >> 4) & 0x0F0F0F0Fu; }
 __device__ inline uint32_t bim4(uint32_t y) { return y & 0x0F0F0F0Fu; }
+// ... and from raw words x (the bias folded into the mask: one v_bitop3 each).
+__device__ inline uint32_t bu4(uint32_t x) { return ((x >> 4) & 0x0F0F0F0Fu) ^ 0x08080808u; }
+__device__ inline uint32_t bw4(uint32_t x) { return (x & 0x0F0F0F0Fu) ^ 0x08080808u; }
 
 // Second GEMM operand from the first, for four samples per dword:
 //   s = (re+8) + (im+8)      = re + im + 16   in 0..30
 //   d = (im+8) - (re+8) + 15 = im - re + 15   in 0..30
-// Bytes never carry or borrow into each other.
+// Bytes never carry or borrow into each other; 15 - r = r ^ 15 for a byte
+// r <= 15, so d is one v_xad_u32.
 __device__ inline uint32_t op_s(uint32_t r, uint32_t i) { return r + i; }
-__device__ inline uint32_t op_d(uint32_t r, uint32_t i) { return (i + 0x0F0F0F0Fu) - r; }
+__device__ inline uint32_t op_d(uint32_t r, uint32_t i) { return (r ^ 0x0F0F0F0Fu) + i; }
 
 // Sum of the four bytes of x, added to acc.
 __device__ inline uint32_t bytesum(uint32_t x, uint32_t acc) {

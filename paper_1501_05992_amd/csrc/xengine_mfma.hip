@@ -55,12 +55,21 @@ namespace corrx {
 // ---- staging of packed samples into LDS ---------------------------------------
 
 // ROWS inputs staged per chunk of TC samples by NT threads.  Stage row r holds
-// the A-operand bytes of one input: 16-byte chunk k = samples 8k..8k+7 as
-// [u(4), w(4), u(4), w(4)], chunks XOR-swizzled per row.  SCALAR_RSRC: read
-// the load descriptors from the first lane (for units whose block indices the
-// compiler cannot prove uniform; a descriptor in vector registers costs a loop
-// per load).
-template <int ROWS, int TC, int NT, bool SCALAR_RSRC = false>
+// the A-operand bytes of one input: 16-byte granule k = samples 8k..8k+7 as
+// [u(4), w(4), u(4), w(4)] (biased parts u = re + 8, w = im + 8), granules
+// XOR-swizzled per row.  With QROWS > 0 the first QROWS rows are also stored
+// in the form Q = [w(4), 15 - u(4), w(4), 15 - u(4)] in a second area after the
+// ROWS rows (the cross units' imaginary-part operand).
+//
+// Per-input sums Su = sum u and Sw = sum w are kept in byte lanes: every
+// store adds two words of at most 15 per byte, so a byte accumulator takes
+// FLUSH chunks (8, or 4 when a thread's two items share their inputs) before it
+// is folded into the LDS totals s_su / s_sw with one v_dot4 per word.
+//
+// SCALAR_RSRC: read the load descriptors from the first lane (for units whose
+// block indices the compiler cannot prove uniform; a descriptor in vector
+// registers costs a loop per load).
+template <int ROWS, int TC, int NT, int QROWS = 0, bool SCALAR_RSRC = false>
 struct Stage {
   static constexpr int QUADS = ROWS / 4;
   static constexpr int GROUPS = TC / 8;              // 8-row groups per chunk
@@ -72,10 +81,14 @@ struct Stage {
   static constexpr bool SHARED_Q = NT % QUADS == 0;
   static constexpr int SUMS = SHARED_Q ? 1 : ITER;
   static constexpr int ROWB = 2 * TC;                // bytes per row and chunk
-  static constexpr int BYTES = ROWS * ROWB;          // one stage buffer
+  static constexpr int PBYTES = ROWS * ROWB;         // the A-form rows of one stage buffer
+  static constexpr int BYTES = (ROWS + QROWS) * ROWB;  // one stage buffer
   static constexpr int GRAN = ROWB / 16;             // 16-byte granules per row and chunk
   static constexpr int KSTEPS = TC / 16;             // K=32 (16-sample) MFMA steps per chunk
+  static constexpr int FLUSH = 255 / (30 * (SHARED_Q ? ITER : 1)) >= 8 ? 8 : 4;
+  static_assert(30 * (SHARED_Q ? ITER : 1) * FLUSH <= 255, "byte sums must not carry");
   static_assert(TC == 64 || TC == 128 || TC == 256, "the unpack is split into four phases over the K-steps of a chunk");
+  static_assert(QROWS % 4 == 0 && QROWS <= ROWS, "Q rows are whole quads of stage rows");
   static constexpr bool FP8 = false;
 
   // Stage quad q -> first input: the first `split` quads start at base0, the
@@ -91,6 +104,7 @@ struct Stage {
   // fourth row) are free of bank conflicts.
   __device__ static int swz(int row) { return (row ^ (row >> 2)) & (GRAN - 1); }
   __device__ static bool has_item(int tid, int k) { return EXACT || tid + k * NT < ITEMS; }
+  __device__ static int quad(int tid, int k) { return (tid + k * NT) % QUADS; }
 
   // Load the 8 rows x 4 inputs of this thread's items of chunk c.
   //   ALIGNED (N % 4 == 0, 4-byte aligned buffer): raw buffer loads through a
@@ -160,122 +174,111 @@ struct Stage {
 
   // Unpack of one chunk, in four phases (one per K-step of the previous
   // chunk).  One item per thread: phases 0/1 transpose rows 0-3 / 4-7
-  // (time-major -> input-major) and bias; phases 2/3 handle inputs 0-1 / 2-3
-  // of the quad -- byte sums and one 16-byte store per input.  Two items per
-  // thread: phases 0/1 transpose / store item 0, phases 2/3 item 1, so only
-  // one item's transposed words are live at a time.  The transposes flag
-  // invalid codes in `bad`; the item's store phase then masks them (a branch
-  // taken only by items that hold one).
+  // (time-major -> input-major); phases 2/3 handle inputs 0-1 / 2-3 of the
+  // quad -- biased parts, byte sums and one 16-byte store per input.  Two
+  // items per thread: phases 0/1 transpose / store item 0, phases 2/3 item 1,
+  // so only one item's transposed words are live at a time.  The transposes
+  // flag invalid codes in `bad`; the item's store phase then masks them (a
+  // branch taken only by items that hold one).  The transposed words x stay
+  // raw (unbiased): the bias is folded into the nibble extraction.
   static_assert(ITER <= 2, "at most two unpack items per thread");
   static constexpr int LOAD_PHASE = ITER == 1 ? 1 : 2;  // last phase that reads the loaded words
 
-  __device__ static void transpose_tq(const uint32_t (&ld)[ITER][8], uint32_t (&y)[8], int k, int tq, uint32_t& bad) {
+  __device__ static void transpose_tq(const uint32_t (&ld)[ITER][8], uint32_t (&x)[8], int k, int tq, uint32_t& bad) {
     uint32_t e0, e1, e2, e3;
     transpose4x4(ld[k][4 * tq], ld[k][4 * tq + 1], ld[k][4 * tq + 2], ld[k][4 * tq + 3], e0, e1, e2, e3);
-    y[tq] = bias4(e0);  // y[2*c + tq]: input c, time quad tq
-    y[2 + tq] = bias4(e1);
-    y[4 + tq] = bias4(e2);
-    y[6 + tq] = bias4(e3);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) bad |= (y[2 * c + tq] - 0x11111111u) & ~y[2 * c + tq];
+    x[tq] = e0;  // x[2*c + tq]: input c, time quad tq
+    x[2 + tq] = e1;
+    x[4 + tq] = e2;
+    x[6 + tq] = e3;
+    const uint32_t kc = vconst(0xEEEEEEEFu);
+    bad |= invalid_flags_raw(e0, kc) | invalid_flags_raw(e1, kc) | invalid_flags_raw(e2, kc) |
+           invalid_flags_raw(e3, kc);
   }
 
-  __device__ static void store_input(const uint32_t (&y)[8], uint8_t* st, int k, int c, uint32_t (&sy)[SUMS][4],
-                                     uint32_t (&sw)[SUMS][4], int tid) {
+  __device__ static void store_input(const uint32_t (&x)[8], uint8_t* st, int k, int c, uint32_t (&bu)[SUMS][4],
+                                     uint32_t (&bw)[SUMS][4], int tid) {
     const int item = tid + k * NT;
     const int q = item % QUADS, g = item / QUADS;
     const int row = 4 * q + c;
-    const uint32_t ya = y[2 * c], yb = y[2 * c + 1];
-    const uint32_t ra = bre4(ya), ia = bim4(ya), rb = bre4(yb), ib = bim4(yb);
+    const uint32_t xa = x[2 * c], xb = x[2 * c + 1];
+    const uint32_t ra = bu4(xa), ia = bw4(xa), rb = bu4(xb), ib = bw4(xb);
     const int ks = SHARED_Q ? 0 : k;
-    sy[ks][c] = bytesum(yb, bytesum(ya, sy[ks][c]));
-    sw[ks][c] = bytesum(ib, bytesum(ia, sw[ks][c]));
-    v4i v;
-    v.x = (int)ra;
-    v.y = (int)ia;
-    v.z = (int)rb;
-    v.w = (int)ib;
-    *reinterpret_cast<v4i*>(st + row * ROWB + ((g ^ swz(row)) << 4)) = v;
+    bu[ks][c] += ra + rb;
+    bw[ks][c] += ia + ib;
+    const int off = row * ROWB + ((g ^ swz(row)) << 4);
+    *reinterpret_cast<v4i*>(st + off) = v4i{(int)ra, (int)ia, (int)rb, (int)ib};
+    if constexpr (QROWS > 0) {
+      if (row < QROWS)
+        *reinterpret_cast<v4i*>(st + PBYTES + off) =
+            v4i{(int)bw4(xa), (int)(ra ^ 0x0F0F0F0Fu), (int)bw4(xb), (int)(rb ^ 0x0F0F0F0Fu)};
+    }
   }
 
   // Rare path: some sample of the item holds the invalid code; replace each
-  // such sample by a zero sample (biased 0x88) before it is stored and summed.
-  __device__ static void mask_item(uint32_t (&y)[8]) {
+  // such sample by a zero sample (raw 0x00, biased 0x88) before it is stored
+  // and summed.
+  __device__ static void mask_item(uint32_t (&x)[8]) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) y[q] = mask_invalid(y[q]);
+    for (int q = 0; q < 8; ++q) x[q] = mask_invalid_raw(x[q]);
   }
 
   template <int PH>
-  __device__ static void unpack_phase(const uint32_t (&ld)[ITER][8], uint32_t (&y)[8], uint8_t* st,
-                                      uint32_t (&sy)[SUMS][4], uint32_t (&sw)[SUMS][4], uint32_t& bad, int tid) {
+  __device__ static void unpack_phase(const uint32_t (&ld)[ITER][8], uint32_t (&x)[8], uint8_t* st,
+                                      uint32_t (&bu)[SUMS][4], uint32_t (&bw)[SUMS][4], uint32_t& bad, int tid) {
     if constexpr (ITER == 1) {
       if (!has_item(tid, 0)) return;
       if constexpr (PH < 2) {
-        transpose_tq(ld, y, 0, PH, bad);
+        transpose_tq(ld, x, 0, PH, bad);
       } else {
-        if (PH == 2 && (bad & 0x88888888u)) mask_item(y);
-        store_input(y, st, 0, 2 * (PH - 2), sy, sw, tid);
-        store_input(y, st, 0, 2 * (PH - 2) + 1, sy, sw, tid);
+        if (PH == 2 && (bad & 0x88888888u)) mask_item(x);
+        store_input(x, st, 0, 2 * (PH - 2), bu, bw, tid);
+        store_input(x, st, 0, 2 * (PH - 2) + 1, bu, bw, tid);
       }
     } else {
       constexpr int k = PH / 2;
       if (!has_item(tid, k)) return;
       if constexpr (PH % 2 == 0) {
-        transpose_tq(ld, y, k, 0, bad);
-        transpose_tq(ld, y, k, 1, bad);
+        transpose_tq(ld, x, k, 0, bad);
+        transpose_tq(ld, x, k, 1, bad);
       } else {
-        if (bad & 0x88888888u) mask_item(y);
+        if (bad & 0x88888888u) mask_item(x);
         bad = 0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) store_input(y, st, k, c, sy, sw, tid);
+        for (int c = 0; c < 4; ++c) store_input(x, st, k, c, bu, bw, tid);
       }
     }
   }
 
-  __device__ static void unpack_all(const uint32_t (&ld)[ITER][8], uint8_t* st, uint32_t (&sy)[SUMS][4],
-                                    uint32_t (&sw)[SUMS][4], uint32_t& bad, int tid) {
-    uint32_t y[8];
-    unpack_phase<0>(ld, y, st, sy, sw, bad, tid);
-    unpack_phase<1>(ld, y, st, sy, sw, bad, tid);
-    unpack_phase<2>(ld, y, st, sy, sw, bad, tid);
-    unpack_phase<3>(ld, y, st, sy, sw, bad, tid);
+  __device__ static void unpack_all(const uint32_t (&ld)[ITER][8], uint8_t* st, uint32_t (&bu)[SUMS][4],
+                                    uint32_t (&bw)[SUMS][4], uint32_t& bad, int tid) {
+    uint32_t x[8];
+    unpack_phase<0>(ld, x, st, bu, bw, bad, tid);
+    unpack_phase<1>(ld, x, st, bu, bw, bad, tid);
+    unpack_phase<2>(ld, x, st, bu, bw, bad, tid);
+    unpack_phase<3>(ld, x, st, bu, bw, bad, tid);
   }
 
   __device__ static v4i read_frag(const uint8_t* st, int row, int chunk) {
     return *reinterpret_cast<const v4i*>(st + row * ROWB + ((chunk ^ swz(row)) << 4));
   }
 
-  // Reduce the per-thread sums into s_sy / s_sw, then turn them into the
-  // correction terms in place: for the single-GEMM form (CROSS false)
-  // e_k = Sy_k + 30 Sw_k and g_k = Sy_k - 2 Sw_k; for the direct complex form
-  // (CROSS true) 8 (Su_k + Sw_k) = (Sy_k + 15 Sw_k) / 2 and
-  // 8 (Sw_k - Su_k) = (17 Sw_k - Sy_k) / 2, with Sy = 16 Su + Sw (both
-  // numerators are even).
-  template <bool CROSS = false>
-  __device__ static void finish_sums(const uint32_t (&sy)[SUMS][4], const uint32_t (&sw)[SUMS][4], uint32_t* s_sy,
-                                     uint32_t* s_sw, int tid) {
+  // Fold the byte accumulators into the LDS totals of Su and Sw and clear them.
+  __device__ static void flush(uint32_t (&bu)[SUMS][4], uint32_t (&bw)[SUMS][4], uint32_t* s_su, uint32_t* s_sw,
+                               int tid) {
 #pragma unroll
     for (int k = 0; k < SUMS; ++k) {
-      if (!has_item(tid, k)) continue;
-      const int q = (tid + k * NT) % QUADS;
+      if (has_item(tid, k)) {
+        const int q = quad(tid, k);
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        atomicAdd(&s_sy[4 * q + cc], sy[k][cc]);
-        atomicAdd(&s_sw[4 * q + cc], sw[k][cc]);
+        for (int c = 0; c < 4; ++c) {
+          atomicAdd(&s_su[4 * q + c], bytesum(bu[k][c], 0u));
+          atomicAdd(&s_sw[4 * q + c], bytesum(bw[k][c], 0u));
+        }
       }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bu[k][c] = bw[k][c] = 0;
     }
-    __syncthreads();
-    for (int k = tid; k < ROWS; k += NT) {
-      const uint32_t y = s_sy[k], w = s_sw[k];
-      if constexpr (CROSS) {
-        s_sy[k] = (y + 15u * w) >> 1;  // non-negative
-        s_sw[k] = (uint32_t)((int32_t)(17u * w - y) >> 1);  // of either sign: arithmetic shift
-      } else {
-        s_sy[k] = y + 30u * w;
-        s_sw[k] = y - 2u * w;
-      }
-    }
-    __syncthreads();
   }
 };
 
@@ -320,16 +323,22 @@ __device__ inline void write_out(int2* out, const int64_t (&pos)[UN], const bool
 // Main loop shared by all unit kinds: prologue (chunk 0 unpacked, chunk 1
 // loaded), then for every chunk the K-steps of the unit (kstep(st, ks)) with
 // the four unpack phases of the next chunk placed after them and the loads of
-// the chunk after that issued once the registers are free.
+// the chunk after that issued once the registers are free.  The int8 stages
+// also add every input's sums of u and w into s_su / s_sw (zeroed by the
+// caller); they are complete once the caller has synchronised after the loop.
 template <class S, bool ALIGNED, class KStep>
 __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, int f, int t0, int t1, int64_t stride,
-                                  int tid, uint8_t* lds,
-                                  uint32_t (&sy)[S::SUMS][4], uint32_t (&sw)[S::SUMS][4], int nchunks, KStep&& kstep) {
+                                  int tid, uint8_t* lds, uint32_t* s_su, uint32_t* s_sw, int nchunks, KStep&& kstep) {
   uint32_t ld[S::ITER][8];
+  uint32_t bu[S::SUMS][4], bw[S::SUMS][4];
+#pragma unroll
+  for (int k = 0; k < S::SUMS; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bu[k][c] = bw[k][c] = 0;
   if (nchunks > 0) {
     uint32_t bad = 0;
     S::template load<ALIGNED>(p, m, f, t0, t1, 0, stride, tid, ld);
-    S::unpack_all(ld, lds, sy, sw, bad, tid);
+    S::unpack_all(ld, lds, bu, bw, bad, tid);
     if (nchunks > 1) S::template load<ALIGNED>(p, m, f, t0, t1, 1, stride, tid, ld);
   }
   __syncthreads();
@@ -339,21 +348,25 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
     const uint8_t* st = lds + (c & 1) * S::BYTES;
     uint8_t* nst = lds + ((c + 1) & 1) * S::BYTES;
     uint32_t bad = 0;
-    uint32_t y[8];
+    uint32_t x[8];
 #pragma unroll
     for (int ks = 0; ks < S::KSTEPS; ++ks) {
       kstep(st, ks);
       // unpack phase PH runs after K-step PH * KSTEPS / 4
       if constexpr (M1) {
-        if (ks == 0 * S::KSTEPS / 4) S::template unpack_phase<0>(ld, y, nst, sy, sw, bad, tid);
-        if (ks == 1 * S::KSTEPS / 4) S::template unpack_phase<1>(ld, y, nst, sy, sw, bad, tid);
-        if (ks == 2 * S::KSTEPS / 4) S::template unpack_phase<2>(ld, y, nst, sy, sw, bad, tid);
-        if (ks == 3 * S::KSTEPS / 4) S::template unpack_phase<3>(ld, y, nst, sy, sw, bad, tid);
+        if (ks == 0 * S::KSTEPS / 4) S::template unpack_phase<0>(ld, x, nst, bu, bw, bad, tid);
+        if (ks == 1 * S::KSTEPS / 4) S::template unpack_phase<1>(ld, x, nst, bu, bw, bad, tid);
+        if (ks == 2 * S::KSTEPS / 4) S::template unpack_phase<2>(ld, x, nst, bu, bw, bad, tid);
+        if (ks == 3 * S::KSTEPS / 4) S::template unpack_phase<3>(ld, x, nst, bu, bw, bad, tid);
       }
       if constexpr (M2) {
         if (ks == S::LOAD_PHASE * S::KSTEPS / 4)
           S::template load<ALIGNED>(p, m, f, t0, t1, c + 2, stride, tid, ld);
       }
+    }
+    if constexpr (M1 && !S::FP8) {
+      // c + 2 chunks unpacked so far
+      if (((c + 2) & (S::FLUSH - 1)) == 0) S::flush(bu, bw, s_su, s_sw, tid);
     }
     __syncthreads();
   };
@@ -366,6 +379,7 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
     ++c;
   }
   if (c < nchunks) step(c, F_{}, F_{});
+  if constexpr (!S::FP8) S::flush(bu, bw, s_su, s_sw, tid);
 }
 
 // ---- diagonal unit -----------------------------------------------------------
@@ -458,7 +472,8 @@ __device__ inline void combine_quadrant(const Problem& p, int f, int ibase, cons
 
 // One diagonal unit: inputs ibase .. ibase+NB-1 of channel f over samples
 // [t0, t1), run by the NT threads whose local index is tid.  lds: G::LDS
-// bytes; s_sy, s_sw: NB words each.
+// bytes; s_sy, s_sw: NB words each (the inputs' sums, then the correction
+// terms e and g).
 template <int NB, int WC, bool ALIGNED, int TC = diag_tc<NB>>
 __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int tid, uint8_t* lds, uint32_t* s_sy,
                          uint32_t* s_sw, int mode) {
@@ -484,16 +499,11 @@ __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int
   for (int x = 0; x < G::FM; ++x)
 #pragma unroll
     for (int z = 0; z < G::FN; ++z) acc[x][z] = v16i{0};
-  uint32_t sy[S::SUMS][4], sw[S::SUMS][4];
-#pragma unroll
-  for (int k = 0; k < S::SUMS; ++k)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) sy[k][c] = sw[k][c] = 0;
 
   const int half = lane >> 5;
   const int rrow = wr * G::TM + (lane & 31), crow = wc * G::TN + (lane & 31);
   const typename S::Map m{ibase, NB / 4, ibase};
-  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, sy, sw, nchunks,
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, nchunks,
                          [&](const uint8_t* st, int ks) {
                            v4i a[G::FM], b[G::FN];
 #pragma unroll
@@ -508,7 +518,15 @@ __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int
                                acc[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[x], b[z], acc[x][z], 0, 0, 0);
                          });
 
-  S::finish_sums(sy, sw, s_sy, s_sw, tid);
+  // correction terms in place: e_k = 16 Su_k + 31 Sw_k, g_k = 16 Su_k - Sw_k
+  // (with Sy = 16 Su + Sw these are Sy + 30 Sw and Sy - 2 Sw)
+  __syncthreads();
+  for (int k = tid; k < NB; k += G::NT) {
+    const uint32_t su = s_sy[k], sw = s_sw[k];
+    s_sy[k] = 16u * su + 31u * sw;
+    s_sw[k] = 16u * su - sw;
+  }
+  __syncthreads();
   const uint32_t tproc = (uint32_t)(nchunks * G::TC);
   int* xa = reinterpret_cast<int*>(lds);
   int* xb = xa + G::XAREA;
@@ -533,23 +551,21 @@ __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int
 // Rows I0 .. I0+127 against columns J0 .. J0+255 of an off-diagonal block
 // pair (every row input above every column input), in the direct complex
 // form rather than the single biased GEMM: with the staged bytes
-// P_k = (u_k, w_k) of every input and Q_i = (w_i, 16 - u_i) formed from a row
-// fragment in registers (two subtractions per 16 bytes; the swap is free),
+// P_k = (u_k, w_k) of every input and the rows also staged as
+// Q_i = (w_i, 15 - u_i),
 //     R_ij = P_i . P_j = Re V_ij + 8 S_i + 8 S_j - 128 T
-//     M_ij = Q_i . P_j = Im V_ij + 8 D_i + 8 S_j
-// with S_k = Su_k + Sw_k and D_k = Sw_k - Su_k (sums of u and w over the T
-// processed samples).  Both products share the column operand, so a K-step
-// reads four fragments for eight MFMAs and converts only the two row ones.
-// 8 waves as 2 x 4 tiles of 64 x 64 baselines, each holding R and M.
+//     M_ij = Q_i . P_j = Im V_ij + 8 (Sw_i - Su_i) + 8 Su_j + 7 Sw_j
+//                      = Im V_ij + 16 Sw_i - 8 S_i + 8 S_j - Sw_j
+// with S_k = Su_k + Sw_k (Su, Sw the sums of u and w over the T processed
+// samples).  Both products share the column operand, so a K-step reads six
+// fragments for eight MFMAs and converts none.  8 waves as 2 x 4 tiles of
+// 64 x 64 baselines, each holding R and M.
 struct CrossGeom {
   static constexpr int NT = 512;
   static constexpr int ROWS = 384;                   // stage rows: 128 of I, then 256 of J
-  static constexpr int LDS = 2 * ROWS * 128;
+  static constexpr int QROWS = 128;                  // the I rows, also in the Q form
+  static constexpr int LDS = 2 * (ROWS + QROWS) * 128;
 };
-
-__device__ inline v4i to_q(v4i a) {
-  return v4i{a.y, (int)(0x10101010u - (uint32_t)a.x), a.w, (int)(0x10101010u - (uint32_t)a.z)};
-}
 
 template <bool ALIGNED>
 __device__ void run_cross(const Problem& p, int f, int I0, int J0, int t0, int t1, int tid, uint8_t* lds,
@@ -558,7 +574,8 @@ __device__ void run_cross(const Problem& p, int f, int I0, int J0, int t0, int t
   // units run in a loop (the persistent kernel), hoisting them out of it would
   // keep them live across the whole unit and exhaust the registers.
   asm volatile("" : "+v"(tid));
-  using S = Stage<CrossGeom::ROWS, 64, CrossGeom::NT, true>;
+  using S = Stage<CrossGeom::ROWS, 64, CrossGeom::NT, CrossGeom::QROWS, true>;
+  static_assert(2 * S::BYTES == CrossGeom::LDS, "two stage buffers");
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave / 4, wc = wave % 4;
   const int nchunks = t1 > t0 ? (t1 - t0 + 63) / 64 : 0;
@@ -575,25 +592,19 @@ __device__ void run_cross(const Problem& p, int f, int I0, int J0, int t0, int t
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int z = 0; z < 2; ++z) re[x][z] = im[x][z] = v16i{0};
-  uint32_t sy[S::SUMS][4], sw[S::SUMS][4];
-#pragma unroll
-  for (int k = 0; k < S::SUMS; ++k)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) sy[k][c] = sw[k][c] = 0;
 
   const int half = lane >> 5;
   const int irow = wr * 64 + (lane & 31), jrow = 128 + wc * 64 + (lane & 31);
   const typename S::Map m{I0, 32, J0};
-  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, sy, sw, nchunks,
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, nchunks,
                          [&](const uint8_t* st, int ks) {
                            v4i a[2], q[2], b[2];
 #pragma unroll
                            for (int x = 0; x < 2; ++x) {
                              a[x] = S::read_frag(st, irow + 32 * x, 2 * ks + half);
+                             q[x] = S::read_frag(st + S::PBYTES, irow + 32 * x, 2 * ks + half);
                              b[x] = S::read_frag(st, jrow + 32 * x, 2 * ks + half);
                            }
-#pragma unroll
-                           for (int x = 0; x < 2; ++x) q[x] = to_q(a[x]);
 #pragma unroll
                            for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -603,17 +614,20 @@ __device__ void run_cross(const Problem& p, int f, int I0, int J0, int t0, int t
                              }
                          });
 
-  S::template finish_sums<true>(sy, sw, s_sy, s_sw, tid);
+  // s_sy[k] <- 8 S_k, s_sw[k] stays Sw_k
+  __syncthreads();
+  for (int k = tid; k < CrossGeom::ROWS; k += CrossGeom::NT) s_sy[k] = 8u * (s_sy[k] + s_sw[k]);
+  __syncthreads();
   const uint32_t tproc = (uint32_t)(nchunks * 64);
   const int64_t nb = tri_index(p.n_inputs, 0);
   int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
-  // Column terms once per column tile: 128 T - 8 S_j for Re, 8 S_j for Im.
+  // Column terms once per column tile: 128 T - 8 S_j for Re, Sw_j - 8 S_j for Im.
   uint32_t cre[2], cim[2];
 #pragma unroll
   for (int z = 0; z < 2; ++z) {
     const int lj = 128 + wc * 64 + 32 * z + (lane & 31);  // stage row of j
     cre[z] = 128u * tproc - s_sy[lj];
-    cim[z] = s_sy[lj];
+    cim[z] = s_sw[lj] - s_sy[lj];
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -631,9 +645,10 @@ __device__ void run_cross(const Problem& p, int f, int I0, int J0, int t0, int t
           const int li = wr * 64 + 32 * x + acc_row(r, lane);  // stage row of i
           const int i = I0 + li;
           ok[rr] = i < p.n_inputs;
-          // Re V = R - 8 S_i - 8 S_j + 128 T,  Im V = M - 8 D_i - 8 S_j
-          val[rr] = make_int2((int)((uint32_t)re[x][z][r] - s_sy[li] + cre[z]),
-                              (int)((uint32_t)im[x][z][r] - s_sw[li] - cim[z]));
+          const uint32_t s8i = s_sy[li];
+          // Re V = R - 8 S_i - 8 S_j + 128 T,  Im V = M - 16 Sw_i + 8 S_i - 8 S_j + Sw_j
+          val[rr] = make_int2((int)((uint32_t)re[x][z][r] - s8i + cre[z]),
+                              (int)((uint32_t)im[x][z][r] - 16u * s_sw[li] + s8i + cim[z]));
           // n_inputs <= 4096: the offset within the channel fits 32 bits
           pos[rr] = (int64_t)(((uint32_t)i * (uint32_t)(i + 1) >> 1) + j);
         }
@@ -669,6 +684,8 @@ struct StageF8 {
   static constexpr int KSTEPS = 2;                   // K=64 (32-sample) MFMA steps per chunk
   static constexpr int LOAD_PHASE = L::LOAD_PHASE;
   static constexpr bool FP8 = true;
+  static constexpr int FLUSH = 8;  // no sums: the unbiased operands need no correction terms
+  __device__ static void flush(uint32_t (&)[SUMS][4], uint32_t (&)[SUMS][4], uint32_t*, uint32_t*, int) {}
   static_assert(ITER == 1, "one unpack item per thread");
   using Map = typename L::Map;
 
@@ -678,13 +695,14 @@ struct StageF8 {
     L::template load<ALIGNED>(p, m, f, t0, t1, c, stride, tid, ld);
   }
 
-  // Two samples (bytes 2h, 2h+1 of y) of one input -> one A dword and one B
-  // dword of E4M3 codes.  u = re + 8, w = im + 8 become f16 via 1024 + u.
-  __device__ static void to_fp8(uint32_t y, int h, uint32_t& a, uint32_t& b) {
+  // Two samples (bytes 2h, 2h+1 of the raw word x) of one input -> one A
+  // dword and one B dword of E4M3 codes.  u = re + 8, w = im + 8 become f16
+  // via 1024 + u.
+  __device__ static void to_fp8(uint32_t x, int h, uint32_t& a, uint32_t& b) {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     typedef short s2 __attribute__((ext_vector_type(2)));
     const uint32_t sel = h ? 0x04030402u : 0x04010400u;
-    const uint32_t u = bre4(y), w = bim4(y);
+    const uint32_t u = bu4(x), w = bw4(x);
     const h2 bias = {(_Float16)1032.0f, (_Float16)1032.0f};
     const h2 re = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, u, sel)) - bias;
     const h2 im = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, w, sel)) - bias;
@@ -698,9 +716,9 @@ struct StageF8 {
     b = __builtin_bit_cast(uint32_t, vb);
   }
 
-  // Phases 0/1: transpose rows 0-3 / 4-7 and bias; phases 2/3: inputs 0-1 /
-  // 2-3 -- invalid samples zeroed (rare branch), conversion, one 16-byte store
-  // of A and one of B per input.
+  // Phases 0/1: transpose rows 0-3 / 4-7; phases 2/3: inputs 0-1 / 2-3 --
+  // invalid samples zeroed (rare branch), conversion, one 16-byte store of A
+  // and one of B per input.
   template <int PH>
   __device__ static void unpack_phase(const uint32_t (&ld)[ITER][8], uint32_t (&y)[8], uint8_t* st,
                                       uint32_t (&)[SUMS][4], uint32_t (&)[SUMS][4], uint32_t& bad, int tid) {
@@ -708,10 +726,7 @@ struct StageF8 {
     if constexpr (PH < 2) {
       L::transpose_tq(ld, y, 0, PH, bad);
     } else {
-      if (PH == 2 && (bad & 0x88888888u)) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) y[k] = mask_invalid(y[k]);
-      }
+      if (PH == 2 && (bad & 0x88888888u)) L::mask_item(y);
       const int q = tid % QUADS, g = tid / QUADS;
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc) {
@@ -777,12 +792,11 @@ __device__ void run_diag_f8(const Problem& p, int f, int ibase, int t0, int t1, 
   for (int x = 0; x < G::FM; ++x)
 #pragma unroll
     for (int z = 0; z < G::FN; ++z) acc[x][z] = v16f{0.0f};
-  uint32_t sy[1][4], sw[1][4];
 
   const int half = lane >> 5;
   const int rrow = wr * G::TM + (lane & 31), crow = wc * G::TN + (lane & 31);
   const typename S::Map m{ibase, 64, ibase};
-  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, sy, sw, nchunks,
+  run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, nchunks,
                          [&](const uint8_t* st, int ks) {
                            v8i a[G::FM], b[G::FN];
 #pragma unroll
@@ -1012,23 +1026,32 @@ __device__ __noinline__ int batch_small_run(const Problem* table, const WorkItem
   return it;
 }
 
-// The two 256-input unit kinds of the batch, each out of line with its own
-// register allocation (inlined side by side in the persistent loop they would
-// have to share one, and spill).
-__device__ __noinline__ void batch_diag256(const Problem* table, WorkItem w, int base_mode, uint8_t* lds,
-                                           uint32_t* s_sy, uint32_t* s_sw) {
-  const Problem p = table[w.array];
-  const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
-  run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
-}
-
-__device__ __noinline__ void batch_cross(const Problem* table, WorkItem w, int base_mode, uint8_t* lds,
-                                         uint32_t* s_sy, uint32_t* s_sw) {
-  const Problem p = table[w.array];
-  const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
-  int I0, J0;
-  pair_decode(w.tile, I0, J0);
-  run_cross<true>(p, w.channel, I0, J0, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
+// Items of one 256-input unit kind (diagonal block or cross unit), run back
+// to back while the queue hands this workgroup items of that kind.  Out of
+// line, each kind with its own register allocation (inlined side by side in
+// the persistent loop they would share one and spill), and called once per run
+// of items so that the call's register saves are paid per run, not per item
+// (the plan orders items of equal cost by kind).  Returns the first item
+// fetched that is of another kind (or past the end).
+template <int KIND>
+__device__ __noinline__ int batch_run256(const Problem* table, const WorkItem* items, int n_items, int* counter,
+                                         int it, int base_mode, uint8_t* lds, uint32_t* s_sy, uint32_t* s_sw,
+                                         int* s_item) {
+  while (it < n_items) {
+    const WorkItem w = batch_item(items, it);
+    if (w.kind != KIND) break;
+    const Problem p = table[w.array];
+    const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
+    if constexpr (KIND == kUnitDiag256) {
+      run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
+    } else {
+      int I0, J0;
+      pair_decode(w.tile, I0, J0);
+      run_cross<true>(p, w.channel, I0, J0, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
+    }
+    it = batch_fetch(counter, s_item);
+  }
+  return it;
 }
 
 // One workgroup per compute unit pulls work items from a device counter until
@@ -1057,10 +1080,9 @@ __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const Wo
       continue;
     }
     if (w.kind == kUnitDiag256)
-      batch_diag256(table, w, base_mode, lds, s_sy, s_sw);
+      it = batch_run256<kUnitDiag256>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
     else
-      batch_cross(table, w, base_mode, lds, s_sy, s_sw);
-    it = batch_fetch(counter, &s_item);
+      it = batch_run256<kUnitPair>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
   }
 }
 
