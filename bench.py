@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-engine and small-config lines")
     ap.add_argument("--cpu-channels", type=int, default=768, help="channels in the oracle's timed sample")
     ap.add_argument("--check-channels", type=int, default=2, help="channels checked against the oracle")
-    ap.add_argument("--only", choices=("uneven_batch", "coarse_channel"),
+    ap.add_argument("--only", choices=("uneven_batch", "coarse_channel", "ceilings"),
                     help="run only this extra workload (for profiling) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one 1 GiB device-to-device copy (calibrates traffic counters)")
@@ -104,7 +104,8 @@ def main():
         import oracle
 
         fn = {"uneven_batch": lambda: uneven_batch(corrx, model, synth, torch, dev, oracle),
-              "coarse_channel": lambda: coarse_channel(corrx, model, synth, torch, dev)}[args.only]
+              "coarse_channel": lambda: coarse_channel(corrx, model, synth, torch, dev),
+              "ceilings": lambda: ceilings(torch, dev)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n, fc, tc = args.n_inputs, args.n_chan, args.n_time
@@ -255,6 +256,7 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
         c.close()
         del acc
         log(f"full band {eng}: {ms:.3f} ms")
+    out["ceilings"] = ceilings(torch, dev)
     out.update(coarse_channel(corrx, model, synth, torch, dev))
     out["uneven_batch"] = uneven_batch(corrx, model, synth, torch, dev, oracle)
     out["pfb_and_output"] = pfb_and_output(corrx, torch, dev, x, n, fc, tc)
@@ -282,6 +284,49 @@ def coarse_channel(corrx, model, synth, torch, dev):
         log(f"coarse channel {eng}: {ms:.4f} ms")
         c.close()
     del x2
+    return out
+
+
+def ceilings(torch, dev, reps=5):
+    """Measured issue-rate ceilings of the two engines' instructions, every
+    compute unit busy, operands in registers (libceiling.so):
+    v_dot4_i32_i8 (plain engine) and v_mfma_i32_32x32x32_i8 (int8 engine),
+    with the shader clock each workgroup saw (shader-clock cycles over
+    100 MHz constant-clock ticks)."""
+    import ctypes
+
+    from paper_1501_05992_amd import build as hip_build
+
+    if not os.path.exists(hip_build.CEILING_LIB):
+        raise RuntimeError("libceiling.so is not built: run python -m paper_1501_05992_amd.build")
+    lib = ctypes.CDLL(hip_build.CEILING_LIB)
+    lib.ceiling_launch.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 3
+    lib.ceiling_dot4_ops.argtypes = lib.ceiling_mfma_ops.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.ceiling_dot4_ops.restype = lib.ceiling_mfma_ops.restype = ctypes.c_double
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    s = torch.cuda.current_stream()
+    out = {}
+    for kind, name, blocks, iters, ops_fn, peak in (
+            (0, "v_dot4_i32_i8", 8 * n_cu, 20000, lib.ceiling_dot4_ops, None),
+            (1, "v_mfma_i32_32x32x32_i8", 4 * n_cu, 10000, lib.ceiling_mfma_ops, PEAK_INT8_TOPS)):
+        res = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
+        clk = torch.zeros(blocks * 2, dtype=torch.int64, device=dev)
+
+        def launch():
+            if lib.ceiling_launch(kind, blocks, iters, 1, ctypes.c_void_p(res.data_ptr()),
+                                  ctypes.c_void_p(clk.data_ptr()), ctypes.c_void_p(s.cuda_stream)) != 0:
+                raise RuntimeError(f"ceiling probe {name}: launch failed")
+
+        ms = time_ms(torch, launch, reps)
+        c = clk.view(blocks, 2).cpu().numpy().astype(np.float64)
+        ghz = float(np.median(c[:, 0] / np.maximum(c[:, 1], 1) * 0.1))
+        tops = ops_fn(blocks, iters) / (ms * 1e-3) / 1e12
+        out[name] = {"ms": round(ms, 4), "tops": round(tops, 2), "workgroups": blocks, "iters": iters,
+                     "shader_ghz": round(ghz, 3)}
+        if peak:
+            out[name]["frac_of_peak"] = round(tops / peak, 4)
+        log(f"ceiling {name}: {tops:.1f} TOPS at {ghz:.2f} GHz")
+        del res, clk
     return out
 
 

@@ -100,14 +100,19 @@ const char *corr_strerror(int status);
  * Create a correlator for n_inputs inputs, n_chan fine channels and n_time
  * samples per corr_xmac call, with the given input layout (Sec. 1.1: the
  * problem is fixed by the number of inputs, channels and the integration).
- * Selects the current HIP device, which must be gfx950; allocates only the
- * host-side handle.  Sizes: 1 <= n_inputs <= 4096, n_chan >= 1, n_time >= 1,
- * N*F*T < 2^40.  Errors: CORRX_EINVAL, CORRX_EDEVICE (no gfx950 device),
- * CORRX_ENOMEM.  On error *out is set to NULL.
+ * Selects the current HIP device, which must be gfx950; allocates the
+ * host-side handle and, when the int8 engine splits the handle's samples into
+ * several time ranges to fill the device (few channels, long integrations),
+ * a device buffer of up to 1 GiB for the partial sums of those ranges
+ * (nsplit - 1 accumulator images; larger needs fall back to atomic adds).
+ * Sizes: 1 <= n_inputs <= 4096, n_chan >= 1, n_time >= 1, N*F*T < 2^40.
+ * Errors: CORRX_EINVAL, CORRX_EDEVICE (no gfx950 device), CORRX_ENOMEM.  On
+ * error *out is set to NULL.
  */
 int corr_create(int n_inputs, int n_chan, int n_time, int layout, corrx_t *out);
 
-/* Free the handle (NULL is accepted).  Does not touch caller memory. */
+/* Free the handle and its device buffer (NULL is accepted).  Does not touch
+ * caller memory; work queued with the handle must have completed. */
 int corr_destroy(corrx_t h);
 
 /* Choose the compute engine (CORRX_ENGINE_*); default AUTO. */
@@ -285,7 +290,7 @@ enum {
     CORRX_TILE_DEFAULT = 0, /* smallest unit that holds the array's inputs */
     CORRX_TILE_UNIT64 = 1,  /* 64-input units, two channels per work item (N <= 64) */
     CORRX_TILE_UNIT128 = 2, /* 128-input units, two channels per work item (N <= 128) */
-    CORRX_TILE_UNIT256 = 3  /* 256-input diagonal blocks plus pair units (any N) */
+    CORRX_TILE_UNIT256 = 3  /* 256-input diagonal blocks plus cross units (any N) */
 };
 int corr_batch_create(const corrx_desc *descs, int n, int engine, const int *tile_cfg,
                       corrx_batch_t *out);

@@ -1,4 +1,5 @@
-"""Build libcorrx.so (HIP, gfx950) in place with hipcc.
+"""Build libcorrx.so (HIP, gfx950) in place with hipcc, and the instruction
+issue-rate probes (libceiling.so) the benchmark measures ceilings with.
 
     python -m paper_1501_05992_amd.build
 
@@ -18,6 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcorrx.so")
 SOURCES = ["api.hip", "batch.hip", "xengine_mfma.hip", "xengine_plain.hip", "dump.hip", "fpfb.hip"]
+CEILING_LIB = os.path.join(HERE, "libceiling.so")
+CEILING_SOURCES = ["ceiling.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-fp32 instructions are disabled for every device compile.
@@ -27,8 +30,14 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 
 def build(verbose: bool = False, save_temps_dir: str | None = None) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
+    _build_one(LIB, SOURCES, verbose, save_temps_dir)
+    _build_one(CEILING_LIB, CEILING_SOURCES, verbose, None)
+    return LIB
+
+
+def _build_one(lib: str, sources: list[str], verbose: bool, save_temps_dir: str | None) -> None:
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = lib + ".tmp"
     # --no-undefined: a missing definition fails the build instead of the load.
     cmd = [HIPCC, *DEVICE_FLAGS, "-shared", "-Wl,--no-undefined", "-I", os.path.join(ROOT, "include"), "-o", tmp,
            *srcs]
@@ -40,11 +49,10 @@ def build(verbose: bool = False, save_temps_dir: str | None = None) -> str:
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libcorrx.so")
+        raise RuntimeError(f"hipcc failed building {os.path.basename(lib)}")
     if verbose and res.stderr.strip():
         sys.stderr.write(res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
 
 
 if __name__ == "__main__":

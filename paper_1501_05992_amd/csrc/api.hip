@@ -16,6 +16,8 @@ struct corrx_ctx {
   int n_cu;
   int64_t samples; // since the last corr_zero
   void* zeroed;    // accumulator last set to zero by corr_zero (while samples == 0)
+  int* part;       // time-split partial sums of the int8 engine (device), or NULL
+  int64_t part_bytes;
 };
 
 namespace {
@@ -49,6 +51,38 @@ int plan_splits(int n_chan, int units_per_chan, int n_time, int64_t target, int 
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+int64_t acc_bytes_of(int n_inputs, int n_chan) { return (int64_t)n_chan * tri_index(n_inputs, 0) * 2 * sizeof(int); }
+
+// Largest partial-sum buffer a handle allocates; beyond it time splits of the
+// int8 engine add atomically.
+constexpr int64_t kMaxHandlePartBytes = 1LL << 30;
+
+// Time splits of the int8 MFMA engine.  With room for nsplit - 1 partial sums
+// (part_cap bytes) a split writes its own image and a second launch adds them,
+// so 256-input units (263 KB of output per channel) split until every compute
+// unit has one; without, splits add atomically and such units split only
+// while fewer than half the compute units would have work.
+struct XmacPlan {
+  int nsplit;
+  int64_t part_bytes;  // 0: no partial sums (one split, or atomic splits)
+};
+
+XmacPlan plan_i8(int n_inputs, int n_chan, int n_time, int n_cu, int64_t part_cap) {
+  const int units = mfma_units_per_channel(n_inputs);
+  const bool large = n_inputs > 128;
+  const int ns = plan_splits(n_chan, units, n_time, large ? n_cu : 2LL * n_cu);
+  if (ns == 1) return {1, 0};
+  const int64_t need = (int64_t)(ns - 1) * acc_bytes_of(n_inputs, n_chan);
+  if (need <= part_cap) return {ns, need};
+  return {plan_splits(n_chan, units, n_time, large ? n_cu / 2 : 2LL * n_cu), 0};
+}
+
+bool valid_shape(int n_inputs, int n_chan, int n_time, int layout) {
+  if (n_inputs < 1 || n_inputs > 4096 || n_chan < 1 || n_time < 1) return false;
+  if (layout != CORRX_LAYOUT_TFI && layout != CORRX_LAYOUT_FTI) return false;
+  return (double)n_inputs * n_chan * n_time < 1099511627776.0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -70,14 +104,19 @@ const char* corr_strerror(int status) {
 int corr_create(int n_inputs, int n_chan, int n_time, int layout, corrx_t* out) {
   if (!out) return CORRX_EINVAL;
   *out = nullptr;
-  if (n_inputs < 1 || n_inputs > 4096 || n_chan < 1 || n_time < 1) return CORRX_EINVAL;
-  if (layout != CORRX_LAYOUT_TFI && layout != CORRX_LAYOUT_FTI) return CORRX_EINVAL;
-  const double bytes = (double)n_inputs * n_chan * n_time;
-  if (bytes >= 1099511627776.0) return CORRX_EINVAL;
+  if (!valid_shape(n_inputs, n_chan, n_time, layout)) return CORRX_EINVAL;
   int dev = 0, n_cu = 0;
   if (!device_ok(&dev, &n_cu)) return CORRX_EDEVICE;
+  const XmacPlan plan = plan_i8(n_inputs, n_chan, n_time, n_cu, kMaxHandlePartBytes);
+  int* part = nullptr;
+  if (plan.part_bytes > 0 && hipMalloc(&part, (size_t)plan.part_bytes) != hipSuccess) return CORRX_ENOMEM;
   corrx_ctx* h = new (std::nothrow) corrx_ctx;
-  if (!h) return CORRX_ENOMEM;
+  if (!h) {
+    (void)hipFree(part);
+    return CORRX_ENOMEM;
+  }
+  h->part = part;
+  h->part_bytes = plan.part_bytes;
   h->n_inputs = n_inputs;
   h->n_chan = n_chan;
   h->n_time = n_time;
@@ -92,6 +131,7 @@ int corr_create(int n_inputs, int n_chan, int n_time, int layout, corrx_t* out) 
 }
 
 int corr_destroy(corrx_t h) {
+  if (h && h->part) (void)hipFree(h->part);
   delete h;
   return CORRX_OK;
 }
@@ -154,13 +194,13 @@ int corr_xmac(corrx_t h, const void* in, void* acc, void* stream) {
     const int nbk = (h->n_inputs + 63) / 64;
     rc = launch_plain(p, plan_splits(h->n_chan, nbk * (nbk + 1) / 2, h->n_time, 2LL * h->n_cu), mode,
                       as_stream(stream));
+  } else if (engine == CORRX_ENGINE_MFMA_F8) {
+    rc = launch_mfma(p, engine, plan_splits(h->n_chan, 1, h->n_time, h->n_cu / 2, kMaxUnitTimeF8), mode,
+                     CORRX_TILE_DEFAULT, nullptr, as_stream(stream));
   } else {
-    const int units = engine == CORRX_ENGINE_MFMA_F8 ? 1 : mfma_units_per_channel(h->n_inputs);
-    const int max_unit = engine == CORRX_ENGINE_MFMA_F8 ? kMaxUnitTimeF8 : kMaxUnitTime;
-    const bool large = engine == CORRX_ENGINE_MFMA_F8 || h->n_inputs > 128;
-    const int64_t target = large ? h->n_cu / 2 : 2LL * h->n_cu;
-    rc = launch_mfma(p, engine, plan_splits(h->n_chan, units, h->n_time, target, max_unit), mode,
-                     CORRX_TILE_DEFAULT, as_stream(stream));
+    const XmacPlan plan = plan_i8(h->n_inputs, h->n_chan, h->n_time, h->n_cu, h->part_bytes);
+    rc = launch_mfma(p, engine, plan.nsplit, mode, CORRX_TILE_DEFAULT, plan.part_bytes ? h->part : nullptr,
+                     as_stream(stream));
   }
   if (rc == CORRX_OK) h->samples += h->n_time;
   return rc;

@@ -20,7 +20,9 @@ struct corrx_batch {
   int grid;
   int n_items;
   WorkItem* d_items;
-  int* d_counter;
+  int* d_counter;  // one queue counter per segment
+  int n_segs;
+  BatchSegment segs[kMaxSegments];
   void* zeroed[kMaxBatch];  // accumulators set to zero by corr_batch_zero and not written since
   int64_t samples[kMaxBatch];  // samples accumulated per array since corr_batch_zero
 };
@@ -67,7 +69,7 @@ double item_cost(int kind, int n_inputs, int samples) {
 int units_of(int kind, int n_inputs) {
   if (kind != kUnitDiag256) return 1;
   const int nb = (n_inputs + 255) / 256;
-  return nb + nb * (nb - 1);  // diagonal blocks, then pair units
+  return nb + nb * (nb - 1);  // diagonal blocks, then cross units
 }
 
 }  // namespace
@@ -164,22 +166,33 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
           items.push_back(w);
         }
   }
-  // Longest first: the dynamic queue then balances the tail.  Items of equal
-  // cost are grouped by kind, so that a workgroup mostly meets runs of one
-  // kind (the kernel switches kinds through an out-of-line call).
+  // Longest first within each unit kind (the dynamic queue then balances the
+  // tail); the kinds form contiguous segments, one persistent launch each, in
+  // the order of their most expensive item.
   std::stable_sort(items.begin(), items.end(), [&](const WorkItem& x, const WorkItem& y) {
-    const double cx = item_cost(x.kind, b->d[x.array].n_inputs, x.t1 - x.t0);
-    const double cy = item_cost(y.kind, b->d[y.array].n_inputs, y.t1 - y.t0);
-    if (cx != cy) return cx > cy;
-    return x.kind < y.kind;
+    return item_cost(x.kind, b->d[x.array].n_inputs, x.t1 - x.t0) >
+           item_cost(y.kind, b->d[y.array].n_inputs, y.t1 - y.t0);
   });
+  int kind_rank[kMaxSegments];
+  for (int k = 0; k < kMaxSegments; ++k) kind_rank[k] = kMaxSegments;
+  int n_kinds = 0;
+  for (const WorkItem& w : items)
+    if (kind_rank[w.kind] == kMaxSegments) kind_rank[w.kind] = n_kinds++;
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const WorkItem& x, const WorkItem& y) { return kind_rank[x.kind] < kind_rank[y.kind]; });
+  b->n_segs = 0;
+  for (size_t k = 0; k < items.size(); ++k) {
+    if (b->n_segs == 0 || b->segs[b->n_segs - 1].kind != items[k].kind)
+      b->segs[b->n_segs++] = BatchSegment{items[k].kind, (int)k, 0};
+    ++b->segs[b->n_segs - 1].count;
+  }
   if (items.size() > 0x7FFFFFFF) {
     delete b;
     return CORRX_EINVAL;
   }
   b->n_items = (int)items.size();
   if (hipMalloc(&b->d_items, sizeof(WorkItem) * items.size()) != hipSuccess ||
-      hipMalloc(&b->d_counter, sizeof(int)) != hipSuccess) {
+      hipMalloc(&b->d_counter, sizeof(int) * kMaxSegments) != hipSuccess) {
     (void)hipFree(b->d_items);
     delete b;
     return CORRX_ENOMEM;
@@ -252,8 +265,8 @@ int corr_batch_xmac(corrx_batch_t b, const void* const* ins, void* const* accs, 
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return CORRX_EDEVICE;
   // Freshly zeroed accumulators (all of them) are overwritten, not added to.
-  const int rc = launch_batch(args, b->d_items, b->n_items, b->d_counter, b->grid, fresh ? kWriteStore : kWriteAdd,
-                              reinterpret_cast<hipStream_t>(stream));
+  const int rc = launch_batch(args, b->d_items, b->segs, b->n_segs, b->d_counter, b->grid,
+                              fresh ? kWriteStore : kWriteAdd, reinterpret_cast<hipStream_t>(stream));
   for (int a = 0; a < b->n; ++a) b->zeroed[a] = nullptr;
   if (rc == CORRX_OK)
     for (int a = 0; a < b->n; ++a) b->samples[a] += b->d[a].n_time;

@@ -147,9 +147,12 @@ enum WriteMode {
 };
 
 // int8 / fp8 MFMA engine over one problem.  nsplit: time splits per channel
-// (each at most kMaxUnitTime samples); atomic accumulation when nsplit > 1.
-int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, hipStream_t s);
-// Work units per channel of the MFMA engine (diagonal blocks + pair units).
+// (each at most kMaxUnitTime samples).  With nsplit > 1 the int8 engine
+// stores splits 1..nsplit-1 into part (nsplit - 1 accumulator images, fully
+// overwritten) and adds them into the accumulator in a second launch; with
+// part == nullptr, and always for fp8, the splits add atomically.
+int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, int* part, hipStream_t s);
+// Work units per channel of the MFMA engine (diagonal blocks + cross units).
 int mfma_units_per_channel(int n_inputs);
 // vector-ALU engine.
 int launch_plain(const Problem& p, int nsplit, int mode, hipStream_t s);
@@ -172,7 +175,7 @@ int launch_beam(const Problem& p, int* out, hipStream_t s);
 // Unit kinds of the batch kernel.
 enum UnitKind {
   kUnitDiag256 = 0,   // one 256-input diagonal block (tile = block index)
-  kUnitPair = 1,      // one pair unit (tile = pair index: block pair * 2 + half)
+  kUnitPair = 1,      // one cross unit (tile = pair index: block pair * 2 + half)
   kUnitDiag128x2 = 2, // two 128-input channels (f, f+1) side by side
   kUnitDiag64x2 = 3   // two 64-input channels side by side
 };
@@ -193,9 +196,18 @@ struct BatchArgs {
   Problem arrays[kMaxBatch];
 };
 
-// base_mode: kWriteStore (all accumulators freshly zeroed) or kWriteAdd; items
-// with time splits always add atomically.
-int launch_batch(const BatchArgs& args, const WorkItem* d_items, int n_items, int* d_counter, int grid,
-                 int base_mode, hipStream_t s);
+// A contiguous run of the work list holding the items of one unit kind.
+struct BatchSegment {
+  int kind;
+  int begin;
+  int count;
+};
+constexpr int kMaxSegments = 4;  // one per unit kind
+
+// One persistent launch per segment (after one launch that resets the
+// segments' counters).  base_mode: kWriteStore (all accumulators freshly
+// zeroed) or kWriteAdd; items with time splits always add atomically.
+int launch_batch(const BatchArgs& args, const WorkItem* d_items, const BatchSegment* segs, int n_segs, int* d_counters,
+                 int grid, int base_mode, hipStream_t s);
 
 }  // namespace corrx

@@ -48,6 +48,8 @@
 //     through LDS so that each lower-triangle element meets its transpose,
 //     then acc += (Re, Im) (read-modify-write, or atomics for time splits).
 
+#include <algorithm>
+
 #include "corrx_internal.h"
 
 namespace corrx {
@@ -852,9 +854,22 @@ template <int NT>
 constexpr int unit_min_blocks = NT >= 512 ? 1 : 2;
 
 // Diagonal units: unit id -> (channel, diagonal block, time split).
+// Where time split sp of a unit writes.  part == nullptr: every split adds
+// atomically into the accumulator.  Otherwise split 0 writes the accumulator
+// in the caller's mode and split sp > 0 stores into partial sum sp - 1 (a
+// whole accumulator image at part + (sp - 1) * accumulator words), which
+// combine_partials adds in a second launch.
+__device__ inline int split_target(Problem& q, int* part, int nsplit, int sp, int mode) {
+  if (nsplit == 1) return mode;
+  if (part == nullptr) return kWriteAtomic;
+  if (sp == 0) return mode;
+  q.acc = part + (int64_t)(sp - 1) * ((int64_t)q.n_chan * tri_index(q.n_inputs, 0) * 2);
+  return kWriteStore;
+}
+
 template <int NB, int WC, bool ALIGNED>
 __global__ __launch_bounds__(128 * WC, unit_min_blocks<128 * WC>) void xmac_diag_i8(Problem p, int nblk, int nsplit,
-                                                                                  int tsplit, int mode) {
+                                                                                  int tsplit, int mode, int* part) {
   using G = DiagGeom<NB, WC>;
   static_assert(G::NT == 128 * WC, "thread count must match the launch bounds");
   __shared__ __attribute__((aligned(16))) uint8_t lds[G::LDS];
@@ -864,8 +879,9 @@ __global__ __launch_bounds__(128 * WC, unit_min_blocks<128 * WC>) void xmac_diag
   u /= nsplit;
   const int blk = u % nblk, f = u / nblk;
   const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
-  run_diag<NB, WC, ALIGNED>(p, f, blk * NB, t0, t1, threadIdx.x, lds, s_sy, s_sw,
-                            nsplit > 1 ? (int)kWriteAtomic : mode);
+  Problem q = p;
+  const int m = split_target(q, part, nsplit, sp, mode);
+  run_diag<NB, WC, ALIGNED>(q, f, blk * NB, t0, t1, threadIdx.x, lds, s_sy, s_sw, m);
 }
 
 // Cross units: unit id -> (channel, (block pair, half), time split).
@@ -880,7 +896,8 @@ __device__ inline void pair_decode(int pu, int& I0, int& J0) {
 }
 
 template <bool ALIGNED>
-__global__ __launch_bounds__(512, 1) void xmac_cross_i8(Problem p, int npair, int nsplit, int tsplit, int mode) {
+__global__ __launch_bounds__(512, 1) void xmac_cross_i8(Problem p, int npair, int nsplit, int tsplit, int mode,
+                                                         int* part) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[CrossGeom::LDS];
   __shared__ uint32_t s_sy[CrossGeom::ROWS], s_sw[CrossGeom::ROWS];
   int u = xcd_remap(blockIdx.x, gridDim.x);
@@ -890,7 +907,28 @@ __global__ __launch_bounds__(512, 1) void xmac_cross_i8(Problem p, int npair, in
   int I0, J0;
   pair_decode(pu, I0, J0);
   const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
-  run_cross<ALIGNED>(p, f, I0, J0, t0, t1, threadIdx.x, lds, s_sy, s_sw, nsplit > 1 ? (int)kWriteAtomic : mode);
+  Problem q = p;
+  const int m = split_target(q, part, nsplit, sp, mode);
+  run_cross<ALIGNED>(q, f, I0, J0, t0, t1, threadIdx.x, lds, s_sy, s_sw, m);
+}
+
+// acc[i] += sum over s < n_part of part[s * n_words + i].  Four words per
+// thread and step where every operand is 16-byte aligned.
+__global__ __launch_bounds__(256) void combine_partials(int* acc, const int* part, int64_t n_words, int n_part,
+                                                        int vec) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n4 = vec ? n_words / 4 : 0;
+  for (int64_t i = i0; i < n4; i += stride) {
+    v4i a = reinterpret_cast<const v4i*>(acc)[i];
+    for (int s = 0; s < n_part; ++s) a += __builtin_nontemporal_load(reinterpret_cast<const v4i*>(part + s * n_words) + i);
+    reinterpret_cast<v4i*>(acc)[i] = a;
+  }
+  for (int64_t i = 4 * n4 + i0; i < n_words; i += stride) {
+    int a = acc[i];
+    for (int s = 0; s < n_part; ++s) a += part[s * n_words + i];
+    acc[i] = a;
+  }
 }
 
 template <bool ALIGNED>
@@ -911,30 +949,41 @@ static bool aligned_problem(const Problem& p) {
 }
 
 template <int NB, int WC>
-static int launch_diag(const Problem& p, int nblk, int nsplit, int mode, hipStream_t s) {
+static int launch_diag(const Problem& p, int nblk, int nsplit, int mode, int* part, hipStream_t s) {
   using G = DiagGeom<NB, WC>;
   const int tsplit = (p.n_time + nsplit - 1) / nsplit;
   const int64_t grid = (int64_t)p.n_chan * nblk * nsplit;
   if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
   if (aligned_problem(p))
     hipLaunchKernelGGL((xmac_diag_i8<NB, WC, true>), dim3((unsigned)grid), dim3(G::NT), 0, s, p, nblk, nsplit,
-                       tsplit, mode);
+                       tsplit, mode, part);
   else
     hipLaunchKernelGGL((xmac_diag_i8<NB, WC, false>), dim3((unsigned)grid), dim3(G::NT), 0, s, p, nblk, nsplit,
-                       tsplit, mode);
+                       tsplit, mode, part);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
-static int launch_cross(const Problem& p, int npair, int nsplit, int mode, hipStream_t s) {
+static int launch_cross(const Problem& p, int npair, int nsplit, int mode, int* part, hipStream_t s) {
   const int tsplit = (p.n_time + nsplit - 1) / nsplit;
   const int64_t grid = (int64_t)p.n_chan * npair * nsplit;
   if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
   if (aligned_problem(p))
     hipLaunchKernelGGL((xmac_cross_i8<true>), dim3((unsigned)grid), dim3(CrossGeom::NT), 0, s, p, npair, nsplit,
-                       tsplit, mode);
+                       tsplit, mode, part);
   else
     hipLaunchKernelGGL((xmac_cross_i8<false>), dim3((unsigned)grid), dim3(CrossGeom::NT), 0, s, p, npair, nsplit,
-                       tsplit, mode);
+                       tsplit, mode, part);
+  return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
+}
+
+static int launch_combine(const Problem& p, int n_part, const int* part, hipStream_t s) {
+  const int64_t n_words = (int64_t)p.n_chan * tri_index(p.n_inputs, 0) * 2;
+  const int vec = ((reinterpret_cast<uintptr_t>(p.acc) | reinterpret_cast<uintptr_t>(part)) & 15) == 0 &&
+                  n_words % 4 == 0;
+  const int64_t items = vec ? n_words / 4 : n_words;
+  const int64_t grid = std::min<int64_t>((items + 255) / 256, 4096);
+  hipLaunchKernelGGL(combine_partials, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(256), 0, s, p.acc, part,
+                     n_words, n_part, vec);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
@@ -957,28 +1006,46 @@ static int launch_f8(const Problem& p, int nsplit, int mode, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
-int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, hipStream_t s) {
+int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, int* part, hipStream_t s) {
   (void)tile_cfg;
   if (engine == CORRX_ENGINE_MFMA_F8) return launch_f8(p, nsplit, mode, s);
   if (engine != CORRX_ENGINE_MFMA_I8) return CORRX_EUNSUPPORTED;
-  if (p.n_inputs <= 64) return launch_diag<64, 2>(p, 1, nsplit, mode, s);
-  if (p.n_inputs <= 128) return launch_diag<128, 2>(p, 1, nsplit, mode, s);
-  const int nb = (p.n_inputs + 255) / 256;
-  int rc = launch_diag<256, 4>(p, nb, nsplit, mode, s);
-  if (rc == CORRX_OK && nb > 1) rc = launch_cross(p, nb * (nb - 1), nsplit, mode, s);
+  if (nsplit == 1) part = nullptr;
+  int rc;
+  if (p.n_inputs <= 64) {
+    rc = launch_diag<64, 2>(p, 1, nsplit, mode, part, s);
+  } else if (p.n_inputs <= 128) {
+    rc = launch_diag<128, 2>(p, 1, nsplit, mode, part, s);
+  } else {
+    const int nb = (p.n_inputs + 255) / 256;
+    rc = launch_diag<256, 4>(p, nb, nsplit, mode, part, s);
+    if (rc == CORRX_OK && nb > 1) rc = launch_cross(p, nb * (nb - 1), nsplit, mode, part, s);
+  }
+  if (rc == CORRX_OK && part) rc = launch_combine(p, nsplit - 1, part, s);
   return rc;
 }
 
-// ---- persistent batch kernel ----------------------------------------------------
+// ---- persistent batch kernels ---------------------------------------------------
+//
+// One persistent launch per unit kind: one workgroup per compute unit pulls
+// the kind's work items (a contiguous segment of the work list, longest first)
+// from the segment's counter until the segment is exhausted.  A kernel per
+// kind keeps each unit inlined with its own register allocation; one kernel
+// switching between kinds would either share one allocation (and spill) or
+// call the units out of line and save their registers on every call.
 
-constexpr int kBatchLds =
-    DiagGeom<256, 4>::LDS > CrossGeom::LDS ? DiagGeom<256, 4>::LDS : CrossGeom::LDS;
 // The batch's 64-input units take 256-sample chunks: with only two units per
 // compute unit (one workgroup of 512 threads), the longer chunks keep four
 // times as many input bytes in flight per unit as 64-sample chunks.
 constexpr int kBatchTc64 = 256;
-static_assert(2 * DiagGeom<128, 2>::LDS <= kBatchLds, "two 128-input units fit side by side");
-static_assert(2 * DiagGeom<64, 2, kBatchTc64>::LDS <= kBatchLds, "two 64-input units fit side by side");
+
+template <int KIND>
+constexpr int batch_lds = KIND == kUnitDiag256   ? DiagGeom<256, 4>::LDS
+                          : KIND == kUnitPair    ? CrossGeom::LDS
+                          : KIND == kUnitDiag128x2 ? 2 * DiagGeom<128, 2>::LDS
+                                                   : 2 * DiagGeom<64, 2, kBatchTc64>::LDS;
+template <int KIND>
+constexpr int batch_rows = KIND == kUnitPair ? CrossGeom::ROWS : 256;
 
 // Next work item of the persistent kernel (same value in every thread).
 __device__ inline int batch_fetch(int* counter, int* s_item) {
@@ -1001,68 +1068,15 @@ __device__ inline WorkItem batch_item(const WorkItem* items, int it) {
   return w;
 }
 
-// Items of the two-channel kinds (64 or 128 inputs).  Kept out of line, with
-// its own register allocation, and it keeps pulling items while they are of
-// its kind, so the call happens once per run of such items.  Returns the
-// first item it fetched that is of another kind (or past the end).
-template <int NB>
-__device__ __noinline__ int batch_small_run(const Problem* table, const WorkItem* items, int n_items, int* counter,
-                                            int it, int base_mode, uint8_t* lds, uint32_t* s_sy, uint32_t* s_sw,
-                                            int* s_item) {
-  constexpr int kind = NB == 64 ? kUnitDiag64x2 : kUnitDiag128x2;
-  while (it < n_items) {
-    const WorkItem w = batch_item(items, it);
-    if (w.kind != kind) break;
-    const Problem p = table[w.array];
-    const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
-    const int tid = threadIdx.x;
-    const int g = tid >> 8, f = w.channel + g;
-    constexpr int TC = NB == 64 ? kBatchTc64 : diag_tc<NB>;
-    run_diag<NB, 2, true, TC>(p, min(f, p.n_chan - 1), 0, w.t0, w.t1, tid & 255,
-                              lds + g * DiagGeom<NB, 2, TC>::LDS, s_sy + NB * g, s_sw + NB * g,
-                              f < p.n_chan ? mode : (int)kWriteNone);
-    it = batch_fetch(counter, s_item);
-  }
-  return it;
-}
-
-// Items of one 256-input unit kind (diagonal block or cross unit), run back
-// to back while the queue hands this workgroup items of that kind.  Out of
-// line, each kind with its own register allocation (inlined side by side in
-// the persistent loop they would share one and spill), and called once per run
-// of items so that the call's register saves are paid per run, not per item
-// (the plan orders items of equal cost by kind).  Returns the first item
-// fetched that is of another kind (or past the end).
+// items / n_items: the kind's segment of the work list.  All arrays must be
+// aligned.  The x2 kinds run two units side by side, on channels f and f+1 of
+// the same array (the second writes nothing past the last channel).
 template <int KIND>
-__device__ __noinline__ int batch_run256(const Problem* table, const WorkItem* items, int n_items, int* counter,
-                                         int it, int base_mode, uint8_t* lds, uint32_t* s_sy, uint32_t* s_sw,
-                                         int* s_item) {
-  while (it < n_items) {
-    const WorkItem w = batch_item(items, it);
-    if (w.kind != KIND) break;
-    const Problem p = table[w.array];
-    const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
-    if constexpr (KIND == kUnitDiag256) {
-      run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
-    } else {
-      int I0, J0;
-      pair_decode(w.tile, I0, J0);
-      run_cross<true>(p, w.channel, I0, J0, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
-    }
-    it = batch_fetch(counter, s_item);
-  }
-  return it;
-}
-
-// One workgroup per compute unit pulls work items from a device counter until
-// the list is exhausted.  Every item is one unit (or two small units side by
-// side, on channels f and f+1 of the same array).  All arrays must be aligned.
 __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const WorkItem* items, int n_items,
                                                          int* counter, int base_mode) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kBatchLds];
-  __shared__ uint32_t s_sy[CrossGeom::ROWS], s_sw[CrossGeom::ROWS];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[batch_lds<KIND>];
+  __shared__ uint32_t s_sy[batch_rows<KIND>], s_sw[batch_rows<KIND>];
   __shared__ int s_item;
-  const int tid = threadIdx.x;
   // The problem table is the first kernel argument: read it in place in the
   // kernel-argument segment (taking the address of the by-value parameter
   // would copy it to private memory).
@@ -1071,27 +1085,60 @@ __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const Wo
   int it = batch_fetch(counter, &s_item);
   while (it < n_items) {
     const WorkItem w = batch_item(items, it);
-    if (w.kind == kUnitDiag64x2) {
-      it = batch_small_run<64>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
-      continue;
+    const Problem p = table[w.array];
+    const int mode = w.atomic ? (int)kWriteAtomic : base_mode;
+    if constexpr (KIND == kUnitDiag256) {
+      run_diag<256, 4, true>(p, w.channel, w.tile * 256, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
+    } else if constexpr (KIND == kUnitPair) {
+      int I0, J0;
+      pair_decode(w.tile, I0, J0);
+      run_cross<true>(p, w.channel, I0, J0, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
+    } else {
+      constexpr int NB = KIND == kUnitDiag64x2 ? 64 : 128;
+      constexpr int TC = NB == 64 ? kBatchTc64 : diag_tc<NB>;
+      const int tid = threadIdx.x;
+      const int g = tid >> 8, f = w.channel + g;
+      run_diag<NB, 2, true, TC>(p, min(f, p.n_chan - 1), 0, w.t0, w.t1, tid & 255,
+                                lds + g * DiagGeom<NB, 2, TC>::LDS, s_sy + NB * g, s_sw + NB * g,
+                                f < p.n_chan ? mode : (int)kWriteNone);
     }
-    if (w.kind == kUnitDiag128x2) {
-      it = batch_small_run<128>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
-      continue;
-    }
-    if (w.kind == kUnitDiag256)
-      it = batch_run256<kUnitDiag256>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
-    else
-      it = batch_run256<kUnitPair>(table, items, n_items, counter, it, base_mode, lds, s_sy, s_sw, &s_item);
+    it = batch_fetch(counter, &s_item);
   }
 }
 
-__global__ void reset_counter(int* counter) { *counter = 0; }
+__global__ void reset_counters(int* counters, int n) {
+  if ((int)threadIdx.x < n) counters[threadIdx.x] = 0;
+}
 
-int launch_batch(const BatchArgs& args, const WorkItem* d_items, int n_items, int* d_counter, int grid,
-                 int base_mode, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, d_counter);
-  hipLaunchKernelGGL(xmac_batch_i8, dim3(grid), dim3(512), 0, s, args, d_items, n_items, d_counter, base_mode);
+int launch_batch(const BatchArgs& args, const WorkItem* d_items, const BatchSegment* segs, int n_segs, int* d_counters,
+                 int grid, int base_mode, hipStream_t s) {
+  if (n_segs < 0 || n_segs > kMaxSegments) return CORRX_EINVAL;
+  if (n_segs == 0) return CORRX_OK;  // no work items
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(kMaxSegments), 0, s, d_counters, n_segs);
+  for (int k = 0; k < n_segs; ++k) {
+    const WorkItem* it = d_items + segs[k].begin;
+    int* ctr = d_counters + k;
+    switch (segs[k].kind) {
+      case kUnitDiag256:
+        hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag256>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count, ctr,
+                           base_mode);
+        break;
+      case kUnitPair:
+        hipLaunchKernelGGL(xmac_batch_i8<kUnitPair>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count, ctr,
+                           base_mode);
+        break;
+      case kUnitDiag128x2:
+        hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag128x2>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count, ctr,
+                           base_mode);
+        break;
+      case kUnitDiag64x2:
+        hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag64x2>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count, ctr,
+                           base_mode);
+        break;
+      default:
+        return CORRX_EINVAL;
+    }
+  }
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 

@@ -137,6 +137,28 @@ def test_coarse_channel_sampled_channels(cx, coarse, engine):
     c.close()
 
 
+def test_coarse_channel_every_channel(cx, oracle_lib, coarse):
+    """One coarse channel with the int8 engine, which splits each channel's
+    samples over two workgroups to give every compute unit work: all 128
+    channels against the oracle after one call (accumulator overwritten) and
+    after a second (partial sums added on top)."""
+    import torch
+
+    n, fc, tc = coarse.n, coarse.fc, coarse.tc
+    want = oracle_lib.xmac(coarse.host, n, fc, tc)
+    c = cx.Correlator(n, fc, tc, cx.CORRX_LAYOUT_TFI, "mfma_i8")
+    acc = c.new_acc(_dev())
+    c.zero(acc)
+    for calls in (1, 2):
+        c.xmac(coarse.x, acc)
+        torch.cuda.synchronize()
+        got = acc.cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, calls * want), f"after {calls} call(s): {np.argwhere(got != calls * want)[:3]}"
+        print(f"all {fc} channels equal the oracle after {calls} call(s)", flush=True)
+    del acc
+    c.close()
+
+
 @pytest.fixture(scope="module")
 def uneven(oracle_lib):
     import torch

@@ -152,6 +152,18 @@ def test_time_split_path(cx, oracle_lib, engine, n):
     _compare(_run(cx, buf, n, fc, tc, engine=engine), oracle_lib.xmac(buf, n, fc, tc), n, f"{engine} split")
 
 
+@pytest.mark.parametrize("n,fc,tc,calls", [(300, 2, 6000, 2), (256, 3, 9000, 3), (64, 1, 50000, 2),
+                                           (129, 1, 30000, 1), (1000, 1, 4000, 2), (2048, 1, 1500, 1)])
+def test_time_split_partial_sums(cx, oracle_lib, n, fc, tc, calls):
+    # time splits of the int8 engine: split 0 writes the accumulator (stored
+    # on the first call after zero, added on later calls), the others store
+    # partial sums that a second launch adds; diagonal blocks and cross units,
+    # ragged last block and ragged last split
+    buf = synth.make_input(5200 + n, n, fc, tc)
+    _compare(_run(cx, buf, n, fc, tc, calls=calls), calls * oracle_lib.xmac(buf, n, fc, tc), n,
+             f"N={n} F={fc} T={tc} x{calls}")
+
+
 @pytest.mark.parametrize("n,fc,tc,calls", [(160, 1030, 200, 1), (256, 1024, 130, 2), (131, 1024, 70, 1)])
 def test_many_channels_every_channel(cx, oracle_lib, n, fc, tc, calls):
     # four or more rounds of units per compute unit, channel counts that do
