@@ -59,7 +59,8 @@ enum {
     CORRX_ENOMEM = -2,       /* host or device allocation failed */
     CORRX_EDEVICE = -3,      /* no usable gfx950 device, or a HIP call / launch failed */
     CORRX_EUNSUPPORTED = -4, /* valid request this library does not serve */
-    CORRX_EOVERFLOW = -5     /* the int32 accumulator could overflow: zero it first */
+    CORRX_EOVERFLOW = -5,    /* the int32 accumulator could overflow: zero it first */
+    CORRX_ESCRATCH = -6      /* corr_xmac_noalloc: the problem needs more than its scratch */
 };
 
 /* Input layouts of the packed sample buffer (N*F*T bytes). */
@@ -146,6 +147,33 @@ int corr_zero(corrx_t h, void *acc, void *stream);
  * accumulator between corr_zero and that call.
  */
 int corr_xmac(corrx_t h, const void *in, void *acc, void *stream);
+
+/* Size of the device scratch the library holds for corr_xmac_noalloc. */
+#define CORRX_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+
+/*
+ * corr_xmac for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  No
+ * handle and no allocation: computes what corr_create(n_inputs, n_chan,
+ * n_time, layout) followed by corr_xmac computes, with the int8 MFMA engine
+ * and the same work plan, and keeps the partial sums of time splits in a
+ * scratch array the library holds on each device (CORRX_NOALLOC_SCRATCH_BYTES,
+ * held until the process ends) instead of a handle's buffer.
+ *   in, acc, stream: as for corr_xmac; acc has n_chan * N(N+1)/2 * 2 int32.
+ *   accumulate: 0 = acc is overwritten with V(in) (no corr_zero needed),
+ *               1 = acc += V(in).
+ * Sizes as for corr_create (CORRX_EINVAL otherwise).  The caller counts the
+ * samples in acc: the int32 bound of corr_xmac applies to the running total,
+ * and one call of more than 21,913,098 samples returns CORRX_EOVERFLOW.  A
+ * shape whose plan needs more partial-sum memory than the scratch returns
+ * CORRX_ESCRATCH; errors enqueue nothing.  Every call on a device shares that
+ * device's scratch, which keeps the last call's contents (each call
+ * overwrites what it reads, so nothing needs clearing): calls that may
+ * overlap on one device, on different streams or from different threads,
+ * race; order them on one stream.
+ */
+int corr_xmac_noalloc(const void *in, void *acc, int n_inputs, int n_chan, int n_time, int layout,
+                      int accumulate, void *stream);
 
 /*
  * Write the visibilities in acc to dst in `order` (CORRX_TRI_*) as `dtype`

@@ -25,6 +25,8 @@ CORRX_ENOMEM = -2
 CORRX_EDEVICE = -3
 CORRX_EUNSUPPORTED = -4
 CORRX_EOVERFLOW = -5
+CORRX_ESCRATCH = -6
+CORRX_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 CORRX_LAYOUT_TFI = 0
 CORRX_LAYOUT_FTI = 1
@@ -49,7 +51,7 @@ ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
 # Exported symbols, in header order.
 SYMBOLS = ("corr_abi_version", "corr_strerror", "corr_create", "corr_destroy", "corr_set_engine",
            "corr_get_engine", "corr_acc_bytes", "corr_dump_count", "corr_zero", "corr_xmac",
-           "corr_dump", "corr_dump_avg", "corr_pfb_ingest", "corr_pfb_remap", "corr_fpfb_create",
+           "corr_xmac_noalloc", "corr_dump", "corr_dump_avg", "corr_pfb_ingest", "corr_pfb_remap", "corr_fpfb_create",
            "corr_fpfb_destroy", "corr_fpfb_workspace_bytes", "corr_fpfb_tables", "corr_fpfb", "corr_samples",
            "corr_beam", "corr_batch_create", "corr_batch_destroy",
            "corr_batch_items", "corr_batch_plan", "corr_batch_zero", "corr_batch_xmac", "corr_batch_samples")
@@ -89,6 +91,7 @@ def lib() -> ctypes.CDLL:
             "corr_dump_count": ([vp, i], sz),
             "corr_zero": ([vp, vp, vp], i),
             "corr_xmac": ([vp, vp, vp, vp], i),
+            "corr_xmac_noalloc": ([vp, vp, i, i, i, i, i, vp], i),
             "corr_dump": ([vp, vp, i, i, vp, vp], i),
             "corr_dump_avg": ([vp, vp, i, i, i, i, vp, vp], i),
             "corr_pfb_ingest": ([vp, ctypes.POINTER(vp), i, vp, vp], i),
@@ -197,6 +200,16 @@ def corr_zero(h: int, acc, stream=None) -> None:
 def corr_xmac(h: int, inp, acc, stream=None) -> None:
     _check(lib().corr_xmac(h, _ptr(inp, what="input"), _ptr(acc, corr_acc_bytes(h), "acc"), _stream(stream)),
            "corr_xmac")
+
+
+def corr_xmac_noalloc(inp, acc, n_inputs: int, n_chan: int, n_time: int, layout: int = CORRX_LAYOUT_TFI,
+                      accumulate: bool = False, stream=None) -> None:
+    """corr_xmac without a handle or any allocation (int8 engine; time-split
+    partial sums in the library's per-device scratch)."""
+    acc_bytes = n_chan * (n_inputs * (n_inputs + 1) // 2) * 2 * 4
+    _check(lib().corr_xmac_noalloc(_ptr(inp, n_inputs * n_chan * n_time, "input"), _ptr(acc, acc_bytes, "acc"),
+                                   n_inputs, n_chan, n_time, layout, int(bool(accumulate)), _stream(stream)),
+           "corr_xmac_noalloc")
 
 
 def corr_dump(h: int, acc, order: int, dtype: int, dst, stream=None) -> None:

@@ -3,6 +3,7 @@
 
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "corrx_internal.h"
@@ -85,6 +86,48 @@ bool valid_shape(int n_inputs, int n_chan, int n_time, int layout) {
 
 }  // namespace
 
+// ---- library-held scratch of corr_xmac_noalloc ----------------------------------
+
+// Partial sums of corr_xmac_noalloc, one copy per device (the code object is
+// loaded once per device).  In host code this name is only a stand-in for
+// the device array: kernels get the device address looked up below.
+constexpr int64_t kScratchBytes = CORRX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) int scratch[kScratchBytes / sizeof(int)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceSetup {
+  bool done;
+  int status;    // CORRX_OK once the address is known
+  int n_cu;
+  int* scratch;  // this device's copy of `scratch`
+};
+
+std::mutex g_setup_mutex;
+DeviceSetup g_setup[kMaxDevices];
+
+// Once per device, with that device current: check it and look up the device
+// address of its copy of `scratch`.
+const DeviceSetup* device_setup() {
+  int d = 0, n_cu = 0;
+  if (!device_ok(&d, &n_cu) || d < 0 || d >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_setup_mutex);
+  DeviceSetup& e = g_setup[d];
+  if (!e.done) {
+    void* ptr = nullptr;
+    const hipError_t rc = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    e.status = (rc == hipSuccess && ptr != nullptr) ? CORRX_OK : CORRX_EDEVICE;
+    e.scratch = static_cast<int*>(ptr);
+    e.n_cu = n_cu;
+    e.done = true;
+  }
+  return &e;
+}
+
+}  // namespace
+
 extern "C" {
 
 int corr_abi_version(void) { return CORRX_ABI_VERSION; }
@@ -97,6 +140,7 @@ const char* corr_strerror(int status) {
     case CORRX_EDEVICE: return "no usable gfx950 device or a HIP call failed";
     case CORRX_EUNSUPPORTED: return "unsupported request";
     case CORRX_EOVERFLOW: return "int32 accumulator could overflow";
+    case CORRX_ESCRATCH: return "problem needs more scratch memory than the no-allocation entry point holds";
     default: return "unknown status";
   }
 }
@@ -204,6 +248,34 @@ int corr_xmac(corrx_t h, const void* in, void* acc, void* stream) {
   }
   if (rc == CORRX_OK) h->samples += h->n_time;
   return rc;
+}
+
+int corr_xmac_noalloc(const void* in, void* acc, int n_inputs, int n_chan, int n_time, int layout, int accumulate,
+                      void* stream) {
+  if (!in || !acc || (accumulate != 0 && accumulate != 1)) return CORRX_EINVAL;
+  if (!valid_shape(n_inputs, n_chan, n_time, layout)) return CORRX_EINVAL;
+  if (n_time > kMaxAccSamples) return CORRX_EOVERFLOW;
+  const DeviceSetup* setup = device_setup();
+  if (!setup || setup->status != CORRX_OK) return CORRX_EDEVICE;
+  // corr_xmac's plan for a handle of this shape; its partial sums must fit.
+  const XmacPlan plan = plan_i8(n_inputs, n_chan, n_time, setup->n_cu, kMaxHandlePartBytes);
+  if (plan.part_bytes > kScratchBytes) return CORRX_ESCRATCH;
+  Problem p;
+  p.in = static_cast<const uint8_t*>(in);
+  p.acc = static_cast<int*>(acc);
+  p.n_inputs = n_inputs;
+  p.n_chan = n_chan;
+  p.n_time = n_time;
+  p.layout = layout;
+  int mode = accumulate ? kWriteAdd : kWriteStore;
+  if (mode == kWriteStore && plan.nsplit > 1 && plan.part_bytes == 0) {
+    // atomic splits add into the accumulator: clear it first (a kernel, no memset)
+    const int rc = launch_zero(p.acc, acc_bytes_of(n_inputs, n_chan) / (int64_t)sizeof(int), as_stream(stream));
+    if (rc != CORRX_OK) return rc;
+    mode = kWriteAdd;
+  }
+  return launch_mfma(p, CORRX_ENGINE_MFMA_I8, plan.nsplit, mode, CORRX_TILE_DEFAULT,
+                     plan.part_bytes ? setup->scratch : nullptr, as_stream(stream));
 }
 
 int corr_dump(corrx_t h, const void* acc, int order, int dtype, void* dst, void* stream) {

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(cx):
 
 
 def test_strerror(cx):
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert cx.corr_strerror(code)
     assert cx.corr_strerror(-99) == "unknown status"
 
@@ -66,6 +66,17 @@ def test_null_handle_calls(cx):
     assert L.corr_destroy(None) == cx.CORRX_OK
     assert L.corr_batch_xmac(None, None, None, None) in (cx.CORRX_EINVAL, cx.CORRX_EUNSUPPORTED)
     assert L.corr_batch_samples(None, 0) == cx.CORRX_EINVAL
+
+
+def test_noalloc_rejects_bad_arguments_before_touching_the_device(cx):
+    L = cx.lib()
+    p = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+    assert L.corr_xmac_noalloc(None, p, 4, 1, 1, 0, 0, None) == cx.CORRX_EINVAL
+    assert L.corr_xmac_noalloc(p, None, 4, 1, 1, 0, 0, None) == cx.CORRX_EINVAL
+    assert L.corr_xmac_noalloc(p, p, 4, 1, 1, 0, 2, None) == cx.CORRX_EINVAL
+    for args in [(0, 1, 1, 0), (5000, 1, 1, 0), (4, 0, 1, 0), (4, 1, 0, 0), (4, 1, 1, 7)]:
+        assert L.corr_xmac_noalloc(p, p, *args, 0, None) == cx.CORRX_EINVAL
+    assert L.corr_xmac_noalloc(p, p, 4, 1, 21913099, 0, 1, None) == cx.CORRX_EOVERFLOW
 
 
 def test_no_gpu_means_edevice(cx):
