@@ -80,8 +80,12 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-engine and small-config lines")
     ap.add_argument("--cpu-channels", type=int, default=768, help="channels in the oracle's timed sample")
     ap.add_argument("--check-channels", type=int, default=2, help="channels checked against the oracle")
-    ap.add_argument("--only", choices=("uneven_batch", "coarse_channel", "ceilings"),
+    ap.add_argument("--only", choices=("uneven_batch", "coarse_channel", "ceilings", "streaming"),
                     help="run only this extra workload (for profiling) and print its JSON")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="uneven batch: built-in tile codes instead of the autotuner's (for profiling)")
+    ap.add_argument("--stream-integrations", type=int, default=100,
+                    help="paced integrations per observation in the streaming run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one 1 GiB device-to-device copy (calibrates traffic counters)")
     return ap.parse_args()
@@ -103,10 +107,13 @@ def main():
     if args.only:
         import oracle
 
-        fn = {"uneven_batch": lambda: uneven_batch(corrx, model, synth, torch, dev, oracle),
+        fn = {"uneven_batch": lambda: uneven_batch(corrx, model, synth, torch, dev, oracle, not args.no_tune),
               "coarse_channel": lambda: coarse_channel(corrx, model, synth, torch, dev),
-              "ceilings": lambda: ceilings(torch, dev)}[args.only]
+              "ceilings": lambda: ceilings(torch, dev),
+              "streaming": lambda: streaming(synth, torch, args.stream_integrations)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
+        if args.copy_probe:
+            copy_probe(torch, dev)
         return
     n, fc, tc = args.n_inputs, args.n_chan, args.n_time
     seed = synth.config_seed(2)
@@ -203,11 +210,7 @@ def main():
         result["roofline"]["traffic_detail"] = tf
     log(f"timed: {ms_step:.3f} ms/step, xmac {xmac_ms:.3f} ms; parity {check}")
     if args.copy_probe:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        copy_probe(torch, dev)
     if not args.no_extras:
         result["extras"] = extras(corrx, model, synth, torch, dev, x, host, n, fc, tc)
 
@@ -219,6 +222,15 @@ def main():
         result["cpu_baseline"] = cpu_baseline(oracle, model, synth, host, n, fc, tc, args.cpu_channels)
 
     print(json.dumps(result), flush=True)
+
+
+def copy_probe(torch, dev):
+    """One 1 GiB device-to-device copy: calibrates the HBM traffic counters."""
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def time_xmac(corrx, torch, c, x, acc, reps):
@@ -306,14 +318,15 @@ def ceilings(torch, dev, reps=5):
     n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
     s = torch.cuda.current_stream()
     out = {}
-    for kind, name, blocks, iters, ops_fn, peak in (
-            (0, "v_dot4_i32_i8", 8 * n_cu, 20000, lib.ceiling_dot4_ops, None),
-            (1, "v_mfma_i32_32x32x32_i8", 4 * n_cu, 10000, lib.ceiling_mfma_ops, PEAK_INT8_TOPS)):
+    for kind, name, seed, blocks, iters, ops_fn, peak in (
+            (0, "v_dot4_i32_i8", 1, 8 * n_cu, 20000, lib.ceiling_dot4_ops, None),
+            (1, "v_mfma_i32_32x32x32_i8 quiet operands", 0, 4 * n_cu, 10000, lib.ceiling_mfma_ops, PEAK_INT8_TOPS),
+            (1, "v_mfma_i32_32x32x32_i8 random operands", 1, 4 * n_cu, 10000, lib.ceiling_mfma_ops, PEAK_INT8_TOPS)):
         res = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
         clk = torch.zeros(blocks * 2, dtype=torch.int64, device=dev)
 
         def launch():
-            if lib.ceiling_launch(kind, blocks, iters, 1, ctypes.c_void_p(res.data_ptr()),
+            if lib.ceiling_launch(kind, blocks, iters, seed, ctypes.c_void_p(res.data_ptr()),
                                   ctypes.c_void_p(clk.data_ptr()), ctypes.c_void_p(s.cuda_stream)) != 0:
                 raise RuntimeError(f"ceiling probe {name}: launch failed")
 
@@ -430,11 +443,21 @@ def pfb_and_output(corrx, torch, dev, x, n, fc, tc):
 STREAM = [("obs256x3072", 256, 3072), ("obs256x768", 256, 768), ("obs512x384", 512, 384), ("obs128x3072", 128, 3072)]
 
 
-def streaming(synth, torch, paced_integrations=26, flat_integrations=6):
+def _rounded(d):
+    if isinstance(d, dict):
+        return {k: _rounded(v) for k, v in d.items() if k != "admissions"}
+    return round(d, 3) if isinstance(d, float) else d
+
+
+def streaming(synth, torch, paced_integrations=100, queued_integrations=8, flat_integrations=6):
     """Four observations fed in 50 ms chunks (500 samples), 0.5 s integrations,
-    accumulators on the device, admission by a device-memory budget that holds
-    only some of them at once.  Paced: chunks released in real time, latency
-    per integration.  Flat out: chunks as fast as the device takes them."""
+    accumulators on the device.
+    Paced: chunks released in real time, all four observations served together
+    for paced_integrations integrations each; latency (last chunk released ->
+    visibilities in host memory) per integration, p50/p99 per observation.
+    Queued: the same, paced, under a device-memory budget that holds only three,
+    so the fourth waits for admission.
+    Flat out: chunks as fast as the device takes them."""
     from paper_1501_05992_amd.service import CHUNK_SAMPLES, GpuBackend, Observation, Service
 
     pools = {}
@@ -452,25 +475,34 @@ def streaming(synth, torch, paced_integrations=26, flat_integrations=6):
 
     be = GpuBackend()
     need = {o.obs_id: be.mem_bytes(o) for o in make(1, [0, 0, 0, 0])}
-    budget = need["obs256x3072"] + need["obs512x384"] + need["obs256x768"]  # the fourth has to wait
-    log(f"streaming: paced, {paced_integrations} integrations per observation, budget {budget / 1e9:.2f} GB")
-    svc = Service(be, budget)
+    everything = sum(need.values())
+    out = {"observations": [list(x) for x in STREAM], "chunk_samples": CHUNK_SAMPLES,
+           "integration_samples": 10 * CHUNK_SAMPLES,
+           "input_gb_per_data_s": round(sum(model_bytes(n, f) for _, n, f in STREAM) / 1e9, 2)}
+    log(f"streaming: paced, all four together, {paced_integrations} integrations each "
+        f"(about {paced_integrations * 0.5 + 1:.0f} s)")
+    svc = Service(be, everything, progress=log, progress_every=100)
     for o in make(paced_integrations, [0.0, 0.25, 0.5, 0.75]):
         svc.submit(o)
     paced = svc.run(paced=True)
-    log(f"streaming paced: p50 {paced['latency_p50_ms']:.2f} ms, p99 {paced['latency_p99_ms']:.2f} ms")
-    svc = Service(be, sum(need.values()))
+    for oid, st in paced["per_observation"].items():
+        log(f"  {oid}: {st['integrations']} integrations, p50 {st['latency_p50_ms']:.2f} ms, "
+            f"p99 {st['latency_p99_ms']:.2f} ms, real-time factor {st['realtime_factor']:.3f}")
+    out["paced"] = {"hbm_budget_bytes": everything, **_rounded(paced)}
+    budget = need["obs256x3072"] + need["obs512x384"] + need["obs256x768"]  # the fourth has to wait
+    log(f"streaming: paced under a budget of {budget / 1e9:.2f} GB (three of four), {queued_integrations} each")
+    svc = Service(be, budget)
+    for o in make(queued_integrations, [0.0, 0.25, 0.5, 0.75]):
+        svc.submit(o)
+    queued = svc.run(paced=True)
+    out["paced_queued"] = {"hbm_budget_bytes": budget, **_rounded(queued)}
+    svc = Service(be, everything)
     for o in make(flat_integrations, [0, 0, 0, 0]):
         svc.submit(o)
     flat = svc.run(paced=False)
     log(f"streaming flat out: {flat['realtime_factor']:.2f}x real time")
-    rate = sum(model_bytes(n, f) for _, n, f in STREAM)
-    return {"observations": [list(x) for x in STREAM], "chunk_samples": CHUNK_SAMPLES,
-            "integration_samples": 10 * CHUNK_SAMPLES, "hbm_budget_bytes": budget,
-            "input_gb_per_data_s": round(rate / 1e9, 2),
-            "paced": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in paced.items()},
-            "flat_out": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in flat.items()
-                         if k != "admissions"}}
+    out["flat_out"] = _rounded(flat)
+    return out
 
 
 def model_bytes(n, f):
@@ -482,7 +514,7 @@ def model_bytes(n, f):
 UNEVEN = [(64, 3072, 10000, 0), (256, 768, 5000, 0), (512, 384, 4000, 0), (2048, 128, 2000, 0)]
 
 
-def uneven_batch(corrx, model, synth, torch, dev, oracle):
+def uneven_batch(corrx, model, synth, torch, dev, oracle, autotune=True):
     """Arrays of 64/256/512/2048 inputs in one persistent launch, tile codes
     from the autotuner; each array also timed alone through corr_xmac."""
     from paper_1501_05992_amd import tune
@@ -493,8 +525,11 @@ def uneven_batch(corrx, model, synth, torch, dev, oracle):
     probe = corrx.Batch(UNEVEN)
     accs = probe.new_accs(dev)
     probe.close()
-    log("autotuning the uneven batch")
-    codes, report = tune.tune_batch(UNEVEN, ins, accs, use_cache=False)
+    if autotune:
+        log("autotuning the uneven batch")
+        codes, report = tune.tune_batch(UNEVEN, ins, accs, use_cache=False)
+    else:
+        codes = [corrx.CORRX_TILE_DEFAULT] * len(UNEVEN)
     b = corrx.Batch(UNEVEN, tile_cfg=codes)
     plan = [b.plan(k) for k in range(len(UNEVEN))]
     b.zero(accs)

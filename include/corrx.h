@@ -118,6 +118,20 @@ int corr_destroy(corrx_t h);
 
 /* Choose the compute engine (CORRX_ENGINE_*); default AUTO. */
 int corr_set_engine(corrx_t h, int engine);
+
+/*
+ * Choose how the int8 engine divides corr_xmac's work (Sec. 3.4.2: the tile
+ * a work unit computes sets its arithmetic intensity), with the tile codes of
+ * corr_batch_create (CORRX_TILE_*, below): the diagonal unit's inputs (64,
+ * 128 or 256; CORRX_EINVAL if it cannot hold n_inputs), time_splits 0 for
+ * the built-in plan or the number of time ranges per channel, and the chunk
+ * length: 64, 128 or 256 samples for 64-input units, 64 or 128 for 128-input
+ * units, 64 for 256-input units (CORRX_EUNSUPPORTED otherwise).
+ * Default 0 (built-in choice); other engines ignore it.  A set-up call: it may
+ * grow the handle's partial-sum buffer for the requested time splits.
+ * tune.py picks codes by measurement.
+ */
+int corr_set_tile(corrx_t h, int tile_cfg);
 /* Engine that corr_xmac will run (AUTO resolved), or a negative status. */
 int corr_get_engine(corrx_t h);
 
@@ -310,9 +324,14 @@ typedef struct {
  * engine: CORRX_ENGINE_MFMA_I8 or AUTO.  Allocates the device work list and
  * the queue counter (freed by corr_batch_destroy).
  * tile_cfg: NULL (built-in choice) or one code per array, chosen by the
- * autotuner: (unit) | (time_splits << 8), with unit a CORRX_TILE_* value
- * (the input block a work item stages) and time_splits 0 for automatic or the
- * number of time ranges per channel.
+ * autotuner: (unit) | (time_splits << 8) | (chunk << 24), with unit a
+ * CORRX_TILE_* value (the input block a work item stages), time_splits 0 for
+ * automatic or the number of time ranges per channel (at most 4096), and
+ * chunk the samples a work item stages at a time: 0 for the unit's default,
+ * 1, 2, 3 for 64, 128, 256.  The batch kernels have 128 and 256 (default) for
+ * 64-input units, 64 (default) and 128 for 128-input units, 64 for 256-input
+ * units; other chunks return CORRX_EUNSUPPORTED, malformed codes
+ * CORRX_EINVAL.
  */
 enum {
     CORRX_TILE_DEFAULT = 0, /* smallest unit that holds the array's inputs */
@@ -328,7 +347,8 @@ int corr_batch_destroy(corrx_batch_t b);
 int64_t corr_batch_items(corrx_batch_t b);
 
 /* The plan of one array: internal unit kind (0: 256-input blocks, 2: 128-input
- * pairs of channels, 3: 64-input pairs of channels) and time splits. */
+ * pairs of channels, 3: 64-input pairs of channels, 4 and 5: the same with
+ * 128-sample chunks) and time splits. */
 int corr_batch_plan(corrx_batch_t b, int array, int *kind, int *splits);
 
 /*

@@ -50,7 +50,7 @@ ENGINES = {"auto": CORRX_ENGINE_AUTO, "plain": CORRX_ENGINE_PLAIN,
 
 # Exported symbols, in header order.
 SYMBOLS = ("corr_abi_version", "corr_strerror", "corr_create", "corr_destroy", "corr_set_engine",
-           "corr_get_engine", "corr_acc_bytes", "corr_dump_count", "corr_zero", "corr_xmac",
+           "corr_set_tile", "corr_get_engine", "corr_acc_bytes", "corr_dump_count", "corr_zero", "corr_xmac",
            "corr_xmac_noalloc", "corr_dump", "corr_dump_avg", "corr_pfb_ingest", "corr_pfb_remap", "corr_fpfb_create",
            "corr_fpfb_destroy", "corr_fpfb_workspace_bytes", "corr_fpfb_tables", "corr_fpfb", "corr_samples",
            "corr_beam", "corr_batch_create", "corr_batch_destroy",
@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
             "corr_create": ([i, i, i, i, ctypes.POINTER(vp)], i),
             "corr_destroy": ([vp], i),
             "corr_set_engine": ([vp, i], i),
+            "corr_set_tile": ([vp, i], i),
             "corr_get_engine": ([vp], i),
             "corr_acc_bytes": ([vp], sz),
             "corr_dump_count": ([vp, i], sz),
@@ -175,6 +176,17 @@ def corr_destroy(h: int) -> None:
 
 def corr_set_engine(h: int, engine: int) -> None:
     _check(lib().corr_set_engine(h, engine), "corr_set_engine")
+
+
+def corr_set_tile(h: int, tile_cfg: int) -> None:
+    _check(lib().corr_set_tile(h, tile_cfg), "corr_set_tile")
+
+
+def tile_code(unit: int = CORRX_TILE_DEFAULT, splits: int = 0, chunk: int = 0) -> int:
+    """Tile code from a unit (CORRX_TILE_*), time splits (0: automatic) and
+    chunk length in samples (0: the unit's default, else 64, 128 or 256)."""
+    k = {0: 0, 64: 1, 128: 2, 256: 3}[chunk]
+    return unit | (splits << 8) | (k << 24)
 
 
 def corr_get_engine(h: int) -> int:
@@ -338,6 +350,9 @@ class Correlator:
 
     def set_engine(self, engine: int | str) -> None:
         corr_set_engine(self.h, ENGINES[engine] if isinstance(engine, str) else engine)
+
+    def set_tile(self, tile_cfg: int) -> None:
+        corr_set_tile(self.h, tile_cfg)
 
     def new_acc(self, device="cuda") -> torch.Tensor:
         nb = self.n_inputs * (self.n_inputs + 1) // 2

@@ -3,6 +3,7 @@
 
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 
@@ -17,8 +18,9 @@ struct corrx_ctx {
   int n_cu;
   int64_t samples; // since the last corr_zero
   void* zeroed;    // accumulator last set to zero by corr_zero (while samples == 0)
+  int tile;        // int8 engine tile code (corr_set_tile)
   int* part;       // time-split partial sums of the int8 engine (device), or NULL
-  int64_t part_bytes;
+  int64_t part_bytes;  // its size
 };
 
 namespace {
@@ -68,13 +70,22 @@ struct XmacPlan {
   int64_t part_bytes;  // 0: no partial sums (one split, or atomic splits)
 };
 
-XmacPlan plan_i8(int n_inputs, int n_chan, int n_time, int n_cu, int64_t part_cap) {
+// forced > 0: that many time ranges (more if a range would exceed the
+// largest unit), whatever the device.
+XmacPlan plan_i8(int n_inputs, int n_chan, int n_time, int n_cu, int64_t part_cap, int forced = 0) {
   const int units = mfma_units_per_channel(n_inputs);
   const bool large = n_inputs > 128;
-  const int ns = plan_splits(n_chan, units, n_time, large ? n_cu : 2LL * n_cu);
+  int ns = forced;
+  if (ns > 0) {
+    ns = std::min(ns, n_time);
+    while ((n_time + ns - 1) / ns > kMaxUnitTime) ++ns;
+  } else {
+    ns = plan_splits(n_chan, units, n_time, large ? n_cu : 2LL * n_cu);
+  }
   if (ns == 1) return {1, 0};
   const int64_t need = (int64_t)(ns - 1) * acc_bytes_of(n_inputs, n_chan);
   if (need <= part_cap) return {ns, need};
+  if (forced > 0) return {ns, 0};
   return {plan_splits(n_chan, units, n_time, large ? n_cu / 2 : 2LL * n_cu), 0};
 }
 
@@ -159,6 +170,7 @@ int corr_create(int n_inputs, int n_chan, int n_time, int layout, corrx_t* out) 
     (void)hipFree(part);
     return CORRX_ENOMEM;
   }
+  h->tile = CORRX_TILE_DEFAULT;
   h->part = part;
   h->part_bytes = plan.part_bytes;
   h->n_inputs = n_inputs;
@@ -184,6 +196,23 @@ int corr_set_engine(corrx_t h, int engine) {
   if (!h) return CORRX_EINVAL;
   if (engine < CORRX_ENGINE_AUTO || engine > CORRX_ENGINE_MFMA_F8) return CORRX_EINVAL;
   h->engine = engine;
+  return CORRX_OK;
+}
+
+int corr_set_tile(corrx_t h, int tile_cfg) {
+  if (!h || tile_cfg < 0 || (tile_cfg >> 28) != 0 || (tile_cfg & 0xFF) > CORRX_TILE_UNIT256) return CORRX_EINVAL;
+  if (mfma_unit_inputs(h->n_inputs, tile_cfg) == 0) return CORRX_EINVAL;
+  if (!mfma_tile_supported(h->n_inputs, tile_cfg)) return CORRX_EUNSUPPORTED;
+  const XmacPlan plan =
+      plan_i8(h->n_inputs, h->n_chan, h->n_time, h->n_cu, kMaxHandlePartBytes, tile_splits(tile_cfg));
+  if (plan.part_bytes > h->part_bytes) {
+    int* part = nullptr;
+    if (hipMalloc(&part, (size_t)plan.part_bytes) != hipSuccess) return CORRX_ENOMEM;
+    if (h->part) (void)hipFree(h->part);
+    h->part = part;
+    h->part_bytes = plan.part_bytes;
+  }
+  h->tile = tile_cfg;
   return CORRX_OK;
 }
 
@@ -242,9 +271,8 @@ int corr_xmac(corrx_t h, const void* in, void* acc, void* stream) {
     rc = launch_mfma(p, engine, plan_splits(h->n_chan, 1, h->n_time, h->n_cu / 2, kMaxUnitTimeF8), mode,
                      CORRX_TILE_DEFAULT, nullptr, as_stream(stream));
   } else {
-    const XmacPlan plan = plan_i8(h->n_inputs, h->n_chan, h->n_time, h->n_cu, h->part_bytes);
-    rc = launch_mfma(p, engine, plan.nsplit, mode, CORRX_TILE_DEFAULT, plan.part_bytes ? h->part : nullptr,
-                     as_stream(stream));
+    const XmacPlan plan = plan_i8(h->n_inputs, h->n_chan, h->n_time, h->n_cu, h->part_bytes, tile_splits(h->tile));
+    rc = launch_mfma(p, engine, plan.nsplit, mode, h->tile, plan.part_bytes ? h->part : nullptr, as_stream(stream));
   }
   if (rc == CORRX_OK) h->samples += h->n_time;
   return rc;

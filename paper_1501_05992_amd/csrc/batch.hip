@@ -47,10 +47,12 @@ double item_cost(int kind, int n_inputs, int samples) {
   double mfma, bytes;
   switch (kind) {
     case kUnitDiag64x2:
+    case kUnitDiag64x2K128:
       mfma = 2.0 * 64 * 64 * samples;
       bytes = 2.0 * n_inputs * samples;
       break;
     case kUnitDiag128x2:
+    case kUnitDiag128x2K128:
       mfma = 2.0 * 128 * 128 * samples;
       bytes = 2.0 * n_inputs * samples;
       break;
@@ -64,6 +66,20 @@ double item_cost(int kind, int n_inputs, int samples) {
       break;
   }
   return std::max(mfma, bytes * 625.0 / 4.0);
+}
+
+// Unit kind of a tile code's unit and chunk length (tc == 0: default), or -1
+// if the kernels have no such variant.
+int unit_kind(int unit, int n_inputs, int tc) {
+  if (unit == CORRX_TILE_UNIT64 || (unit == CORRX_TILE_DEFAULT && n_inputs <= 64)) {
+    if (tc == 0 || tc == 256) return kUnitDiag64x2;
+    return tc == 128 ? kUnitDiag64x2K128 : -1;
+  }
+  if (unit == CORRX_TILE_UNIT128 || (unit == CORRX_TILE_DEFAULT && n_inputs <= 128)) {
+    if (tc == 0 || tc == 64) return kUnitDiag128x2;
+    return tc == 128 ? kUnitDiag128x2K128 : -1;
+  }
+  return (tc == 0 || tc == 64) ? kUnitDiag256 : -1;
 }
 
 int units_of(int kind, int n_inputs) {
@@ -89,10 +105,11 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
     const int64_t stride = d.layout == CORRX_LAYOUT_TFI ? (int64_t)d.n_chan * d.n_inputs : d.n_inputs;
     const int unit = tile_cfg ? (tile_cfg[a] & 0xFF) : CORRX_TILE_DEFAULT;
     if (tile_cfg) {
-      const int spl = (tile_cfg[a] >> 8) & 0xFFFF;
-      if (unit > CORRX_TILE_UNIT256 || spl > 4096) return CORRX_EINVAL;
+      const int spl = tile_splits(tile_cfg[a]);
+      if (unit > CORRX_TILE_UNIT256 || spl > 4096 || (tile_cfg[a] >> 28) != 0) return CORRX_EINVAL;
       if ((unit == CORRX_TILE_UNIT64 && d.n_inputs > 64) || (unit == CORRX_TILE_UNIT128 && d.n_inputs > 128))
         return CORRX_EINVAL;
+      if (unit_kind(unit, d.n_inputs, tile_chunk_samples(tile_cfg[a])) < 0) return CORRX_EUNSUPPORTED;
     }
     // one chunk of rows (256 for 64-input units, else 128 at most) must span
     // less than 2^31 bytes
@@ -114,11 +131,7 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
     const corrx_desc& d = descs[a];
     b->d[a] = d;
     const int unit = tile_cfg ? (tile_cfg[a] & 0xFF) : CORRX_TILE_DEFAULT;
-    int kind = kUnitDiag256;
-    if (unit == CORRX_TILE_UNIT64 || (unit == CORRX_TILE_DEFAULT && d.n_inputs <= 64))
-      kind = kUnitDiag64x2;
-    else if (unit == CORRX_TILE_UNIT128 || (unit == CORRX_TILE_DEFAULT && d.n_inputs <= 128))
-      kind = kUnitDiag128x2;
+    const int kind = unit_kind(unit, d.n_inputs, tile_cfg ? tile_chunk_samples(tile_cfg[a]) : 0);
     b->kind[a] = kind;
     const int per_item_chan = kind == kUnitDiag256 ? 1 : 2;
     const int64_t items = (int64_t)((d.n_chan + per_item_chan - 1) / per_item_chan) * units_of(kind, d.n_inputs);
@@ -134,7 +147,7 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
   for (int a = 0; a < n; ++a) {
     const corrx_desc& d = descs[a];
     const int kind = b->kind[a];
-    int spl = tile_cfg ? ((tile_cfg[a] >> 8) & 0xFFFF) : 0;
+    int spl = tile_cfg ? tile_splits(tile_cfg[a]) : 0;
     if (spl == 0) {
       spl = 1;
       while (item_cost(kind, d.n_inputs, (d.n_time + spl - 1) / spl) > target && d.n_time / (2 * spl) >= 512)

@@ -57,12 +57,15 @@ __global__ __launch_bounds__(256) void dot4_probe(int* out, long long* clk, int 
 
 constexpr int kAccs = 4;  // independent MFMA accumulators per wave
 
+// seed 0: every operand byte 1 (quiet operands); otherwise hashed bytes
+// (every bit toggling): the matrix cores' power, and so the clock under the
+// power limit, depends on the operand data.
 __global__ __launch_bounds__(256) void mfma_probe(int* out, long long* clk, int iters, int seed) {
   const int lane = (int)threadIdx.x;
   v4i a, b;
   for (int e = 0; e < 4; ++e) {
-    a[e] = (seed + e) * 0x01030507 ^ lane;
-    b[e] = (seed - e) * 0x07050301 + lane;
+    a[e] = seed == 0 ? 0x01010101 : (seed + e) * 0x01030507 ^ lane;
+    b[e] = seed == 0 ? 0x01010101 : (seed - e) * 0x07050301 + lane;
   }
   v16i acc[kAccs];
 #pragma unroll

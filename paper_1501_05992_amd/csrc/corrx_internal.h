@@ -154,6 +154,16 @@ enum WriteMode {
 int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, int* part, hipStream_t s);
 // Work units per channel of the MFMA engine (diagonal blocks + cross units).
 int mfma_units_per_channel(int n_inputs);
+// Tile codes (include/corrx.h): the inputs of the diagonal unit a code
+// selects for n_inputs (0 if it cannot hold them), whether the int8 engine
+// serves the code, and the code's chunk length in samples (0 = default).
+int mfma_unit_inputs(int n_inputs, int tile_cfg);
+bool mfma_tile_supported(int n_inputs, int tile_cfg);
+inline int tile_chunk_samples(int tile_cfg) {
+  const int k = (tile_cfg >> 24) & 0xF;
+  return k == 0 ? 0 : 32 << k;
+}
+inline int tile_splits(int tile_cfg) { return (tile_cfg >> 8) & 0xFFFF; }
 // vector-ALU engine.
 int launch_plain(const Problem& p, int nsplit, int mode, hipStream_t s);
 // accumulator fill, dump and incoherent beam.
@@ -174,11 +184,14 @@ int launch_beam(const Problem& p, int* out, hipStream_t s);
 
 // Unit kinds of the batch kernel.
 enum UnitKind {
-  kUnitDiag256 = 0,   // one 256-input diagonal block (tile = block index)
-  kUnitPair = 1,      // one cross unit (tile = pair index: block pair * 2 + half)
-  kUnitDiag128x2 = 2, // two 128-input channels (f, f+1) side by side
-  kUnitDiag64x2 = 3   // two 64-input channels side by side
+  kUnitDiag256 = 0,        // one 256-input diagonal block (tile = block index), 64-sample chunks
+  kUnitPair = 1,           // one cross unit (tile = pair index: block pair * 2 + half), 64-sample chunks
+  kUnitDiag128x2 = 2,      // two 128-input channels (f, f+1) side by side, 64-sample chunks
+  kUnitDiag64x2 = 3,       // two 64-input channels side by side, 256-sample chunks
+  kUnitDiag128x2K128 = 4,  // as kUnitDiag128x2 with 128-sample chunks
+  kUnitDiag64x2K128 = 5    // as kUnitDiag64x2 with 128-sample chunks
 };
+constexpr int kUnitKinds = 6;
 
 constexpr int kMaxBatch = 64;
 
@@ -202,7 +215,7 @@ struct BatchSegment {
   int begin;
   int count;
 };
-constexpr int kMaxSegments = 4;  // one per unit kind
+constexpr int kMaxSegments = kUnitKinds;  // one per unit kind
 
 // One persistent launch per segment (after one launch that resets the
 // segments' counters).  base_mode: kWriteStore (all accumulators freshly

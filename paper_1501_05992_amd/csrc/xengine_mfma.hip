@@ -867,10 +867,10 @@ __device__ inline int split_target(Problem& q, int* part, int nsplit, int sp, in
   return kWriteStore;
 }
 
-template <int NB, int WC, bool ALIGNED>
+template <int NB, int WC, bool ALIGNED, int TC>
 __global__ __launch_bounds__(128 * WC, unit_min_blocks<128 * WC>) void xmac_diag_i8(Problem p, int nblk, int nsplit,
                                                                                   int tsplit, int mode, int* part) {
-  using G = DiagGeom<NB, WC>;
+  using G = DiagGeom<NB, WC, TC>;
   static_assert(G::NT == 128 * WC, "thread count must match the launch bounds");
   __shared__ __attribute__((aligned(16))) uint8_t lds[G::LDS];
   __shared__ uint32_t s_sy[NB], s_sw[NB];
@@ -881,7 +881,7 @@ __global__ __launch_bounds__(128 * WC, unit_min_blocks<128 * WC>) void xmac_diag
   const int t0 = sp * tsplit, t1 = min(p.n_time, t0 + tsplit);
   Problem q = p;
   const int m = split_target(q, part, nsplit, sp, mode);
-  run_diag<NB, WC, ALIGNED>(q, f, blk * NB, t0, t1, threadIdx.x, lds, s_sy, s_sw, m);
+  run_diag<NB, WC, ALIGNED, TC>(q, f, blk * NB, t0, t1, threadIdx.x, lds, s_sy, s_sw, m);
 }
 
 // Cross units: unit id -> (channel, (block pair, half), time split).
@@ -948,19 +948,37 @@ static bool aligned_problem(const Problem& p) {
          128 * stride + p.n_inputs < 0x7FFFFFFF;
 }
 
-template <int NB, int WC>
+template <int NB, int WC, int TC>
 static int launch_diag(const Problem& p, int nblk, int nsplit, int mode, int* part, hipStream_t s) {
-  using G = DiagGeom<NB, WC>;
+  using G = DiagGeom<NB, WC, TC>;
   const int tsplit = (p.n_time + nsplit - 1) / nsplit;
   const int64_t grid = (int64_t)p.n_chan * nblk * nsplit;
   if (grid > 0x7FFFFFFF) return CORRX_EINVAL;
   if (aligned_problem(p))
-    hipLaunchKernelGGL((xmac_diag_i8<NB, WC, true>), dim3((unsigned)grid), dim3(G::NT), 0, s, p, nblk, nsplit,
+    hipLaunchKernelGGL((xmac_diag_i8<NB, WC, true, TC>), dim3((unsigned)grid), dim3(G::NT), 0, s, p, nblk, nsplit,
                        tsplit, mode, part);
   else
-    hipLaunchKernelGGL((xmac_diag_i8<NB, WC, false>), dim3((unsigned)grid), dim3(G::NT), 0, s, p, nblk, nsplit,
+    hipLaunchKernelGGL((xmac_diag_i8<NB, WC, false, TC>), dim3((unsigned)grid), dim3(G::NT), 0, s, p, nblk, nsplit,
                        tsplit, mode, part);
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
+}
+
+// Diagonal units of NB inputs with TC-sample chunks (tc == 0: the default).
+template <int NB, int WC>
+static int launch_diag_tc(const Problem& p, int nblk, int nsplit, int mode, int* part, int tc, hipStream_t s) {
+  if (tc == 0) tc = diag_tc<NB>;
+  // 256-input units hold their loads in flight for 64-sample chunks only
+  // (longer chunks spill registers); 64-input units take up to 256.
+  switch (tc) {
+    case 64: return launch_diag<NB, WC, 64>(p, nblk, nsplit, mode, part, s);
+    case 128:
+      if constexpr (NB <= 128) return launch_diag<NB, WC, 128>(p, nblk, nsplit, mode, part, s);
+      return CORRX_EUNSUPPORTED;
+    case 256:
+      if constexpr (NB == 64) return launch_diag<NB, WC, 256>(p, nblk, nsplit, mode, part, s);
+      return CORRX_EUNSUPPORTED;
+    default: return CORRX_EUNSUPPORTED;
+  }
 }
 
 static int launch_cross(const Problem& p, int npair, int nsplit, int mode, int* part, hipStream_t s) {
@@ -1006,19 +1024,40 @@ static int launch_f8(const Problem& p, int nsplit, int mode, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? CORRX_OK : CORRX_EDEVICE;
 }
 
+int mfma_unit_inputs(int n_inputs, int tile_cfg) {
+  switch (tile_cfg & 0xFF) {
+    case CORRX_TILE_DEFAULT: return n_inputs <= 64 ? 64 : n_inputs <= 128 ? 128 : 256;
+    case CORRX_TILE_UNIT64: return n_inputs <= 64 ? 64 : 0;
+    case CORRX_TILE_UNIT128: return n_inputs <= 128 ? 128 : 0;
+    case CORRX_TILE_UNIT256: return 256;
+    default: return 0;
+  }
+}
+
+bool mfma_tile_supported(int n_inputs, int tile_cfg) {
+  const int nb = mfma_unit_inputs(n_inputs, tile_cfg);
+  const int tc = tile_chunk_samples(tile_cfg);
+  if (nb == 0 || (tile_cfg >> 28) != 0) return false;
+  if (tc == 0) return true;
+  if (tc != 64 && tc != 128 && tc != 256) return false;
+  if (nb == 256) return tc == 64;
+  return tc <= (nb == 64 ? 256 : 128);
+}
+
 int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg, int* part, hipStream_t s) {
-  (void)tile_cfg;
   if (engine == CORRX_ENGINE_MFMA_F8) return launch_f8(p, nsplit, mode, s);
   if (engine != CORRX_ENGINE_MFMA_I8) return CORRX_EUNSUPPORTED;
+  if (!mfma_tile_supported(p.n_inputs, tile_cfg)) return CORRX_EUNSUPPORTED;
   if (nsplit == 1) part = nullptr;
+  const int unit = mfma_unit_inputs(p.n_inputs, tile_cfg), tc = tile_chunk_samples(tile_cfg);
   int rc;
-  if (p.n_inputs <= 64) {
-    rc = launch_diag<64, 2>(p, 1, nsplit, mode, part, s);
-  } else if (p.n_inputs <= 128) {
-    rc = launch_diag<128, 2>(p, 1, nsplit, mode, part, s);
+  if (unit == 64) {
+    rc = launch_diag_tc<64, 2>(p, 1, nsplit, mode, part, tc, s);
+  } else if (unit == 128) {
+    rc = launch_diag_tc<128, 2>(p, 1, nsplit, mode, part, tc, s);
   } else {
     const int nb = (p.n_inputs + 255) / 256;
-    rc = launch_diag<256, 4>(p, nb, nsplit, mode, part, s);
+    rc = launch_diag_tc<256, 4>(p, nb, nsplit, mode, part, tc, s);
     if (rc == CORRX_OK && nb > 1) rc = launch_cross(p, nb * (nb - 1), nsplit, mode, part, s);
   }
   if (rc == CORRX_OK && part) rc = launch_combine(p, nsplit - 1, part, s);
@@ -1040,10 +1079,15 @@ int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg
 constexpr int kBatchTc64 = 256;
 
 template <int KIND>
-constexpr int batch_lds = KIND == kUnitDiag256   ? DiagGeom<256, 4>::LDS
-                          : KIND == kUnitPair    ? CrossGeom::LDS
-                          : KIND == kUnitDiag128x2 ? 2 * DiagGeom<128, 2>::LDS
-                                                   : 2 * DiagGeom<64, 2, kBatchTc64>::LDS;
+constexpr int batch_nb = (KIND == kUnitDiag64x2 || KIND == kUnitDiag64x2K128) ? 64
+                         : (KIND == kUnitDiag128x2 || KIND == kUnitDiag128x2K128) ? 128 : 256;
+template <int KIND>
+constexpr int batch_tc = KIND == kUnitDiag64x2 ? kBatchTc64
+                         : (KIND == kUnitDiag64x2K128 || KIND == kUnitDiag128x2K128) ? 128 : 64;
+template <int KIND>
+constexpr int batch_lds = KIND == kUnitDiag256 ? DiagGeom<256, 4>::LDS
+                          : KIND == kUnitPair  ? CrossGeom::LDS
+                                               : 2 * DiagGeom<batch_nb<KIND>, 2, batch_tc<KIND>>::LDS;
 template <int KIND>
 constexpr int batch_rows = KIND == kUnitPair ? CrossGeom::ROWS : 256;
 
@@ -1094,8 +1138,8 @@ __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const Wo
       pair_decode(w.tile, I0, J0);
       run_cross<true>(p, w.channel, I0, J0, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw, mode);
     } else {
-      constexpr int NB = KIND == kUnitDiag64x2 ? 64 : 128;
-      constexpr int TC = NB == 64 ? kBatchTc64 : diag_tc<NB>;
+      constexpr int NB = batch_nb<KIND>;
+      constexpr int TC = batch_tc<KIND>;
       const int tid = threadIdx.x;
       const int g = tid >> 8, f = w.channel + g;
       run_diag<NB, 2, true, TC>(p, min(f, p.n_chan - 1), 0, w.t0, w.t1, tid & 255,
@@ -1134,6 +1178,14 @@ int launch_batch(const BatchArgs& args, const WorkItem* d_items, const BatchSegm
       case kUnitDiag64x2:
         hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag64x2>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count, ctr,
                            base_mode);
+        break;
+      case kUnitDiag128x2K128:
+        hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag128x2K128>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count,
+                           ctr, base_mode);
+        break;
+      case kUnitDiag64x2K128:
+        hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag64x2K128>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count,
+                           ctr, base_mode);
         break;
       default:
         return CORRX_EINVAL;

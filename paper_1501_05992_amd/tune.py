@@ -1,15 +1,19 @@
-"""Autotuner of the persistent batched launch.
+"""Autotuner of the int8 engine's tiles, for the persistent batched launch
+and for one correlator.
 
-For every array of a batch it measures a small set of tile codes -- the input
-block a work item stages (64, 128 or 256 inputs; smaller blocks only for
-arrays that fit) times the number of time ranges per channel (automatic, 1, 2,
-4, 8) -- each as one persistent launch on the real inputs, and keeps the
-fastest.  Results are cached in a JSON file keyed by device architecture and
-array shape, so a later batch with the same shapes skips the search.
+A tile code (include/corrx.h) names the input block a work unit stages (64,
+128 or 256 inputs; smaller blocks only for arrays that fit), the number of
+time ranges per channel (automatic, 1, 2, 4, 8) and the samples a unit stages
+at a time (the K-chunk: 64, 128 or 256, where the kernels have that variant).
+The tuner measures each candidate on the real inputs and keeps the fastest:
+for a batch, every array alone as a one-array persistent launch; for a
+correlator, corr_xmac with corr_set_tile.  Results are cached in a JSON file
+keyed by device architecture, engine, path and array shape, so a later run
+with the same shapes skips the search.
 
-The paper fixes its tile shape at compile time for one array (Sec. 3.3.2,
-footnote on compile-time parameters); here the shape is chosen per array at
-run time.
+The paper fixes its tile shape at compile time for one array (Sec. 3.3.3,
+footnote on compile-time parameters; Sec. 3.4.2 on the tile's arithmetic
+intensity); here the shape is chosen per array at run time.
 """
 
 from __future__ import annotations
@@ -25,6 +29,12 @@ from . import corrx
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "corrx", "tune.json")
 SPLITS = (0, 1, 2, 4, 8)
 
+# K-chunk lengths (samples) each unit has kernels for, first the default.
+BATCH_CHUNKS = {corrx.CORRX_TILE_UNIT64: (0, 128), corrx.CORRX_TILE_UNIT128: (0, 128),
+                corrx.CORRX_TILE_UNIT256: (0,)}
+XMAC_CHUNKS = {corrx.CORRX_TILE_UNIT64: (0, 64, 256), corrx.CORRX_TILE_UNIT128: (0, 128),
+               corrx.CORRX_TILE_UNIT256: (0,)}
+
 
 def cache_path() -> str:
     return os.environ.get("CORRX_TUNE_CACHE", DEFAULT_CACHE)
@@ -34,18 +44,24 @@ def _arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
-def _key(desc) -> str:
+def _key(desc, engine: str = "mfma_i8", path: str = "batch", arch: str | None = None) -> str:
     n, f, t, lay = desc
-    return f"{_arch()}|N{n}|F{f}|T{t}|L{lay}"
+    return f"{arch or _arch()}|{engine}|{path}|N{n}|F{f}|T{t}|L{lay}"
 
 
-def candidates(n_inputs: int) -> list[int]:
+def _units(n_inputs: int) -> list[int]:
     units = [corrx.CORRX_TILE_UNIT256]
     if n_inputs <= 128:
         units.append(corrx.CORRX_TILE_UNIT128)
     if n_inputs <= 64:
         units.append(corrx.CORRX_TILE_UNIT64)
-    return [u | (s << 8) for u in units for s in SPLITS]
+    return units
+
+
+def candidates(n_inputs: int, path: str = "batch") -> list[int]:
+    """Tile codes worth measuring for an array of n_inputs inputs."""
+    chunks = BATCH_CHUNKS if path == "batch" else XMAC_CHUNKS
+    return [corrx.tile_code(u, s, c) for u in _units(n_inputs) for c in chunks[u] for s in SPLITS]
 
 
 def measure(descs, tile_cfg, ins, accs, reps: int = 3) -> float:
@@ -66,6 +82,28 @@ def measure(descs, tile_cfg, ins, accs, reps: int = 3) -> float:
     return float(np.median(times))
 
 
+def measure_xmac(desc, code: int, inp, acc, reps: int = 3) -> float:
+    """Median time (ms) of corr_xmac with tile code `code`."""
+    n, f, t, lay = desc
+    c = corrx.Correlator(n, f, t, lay, "mfma_i8")
+    c.set_tile(code)
+    stream = torch.cuda.current_stream()
+    c.zero(acc)
+    c.xmac(inp, acc)  # warm-up
+    times = []
+    for _ in range(reps):
+        c.zero(acc)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        c.xmac(inp, acc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    c.close()
+    return float(np.median(times))
+
+
 def _load_cache(path: str) -> dict:
     try:
         with open(path) as fh:
@@ -82,6 +120,22 @@ def _save_cache(path: str, data: dict) -> None:
     os.replace(tmp, path)
 
 
+def _search(key, cache, codes, timer, log):
+    times = {}
+    for code in codes:
+        try:
+            times[str(code)] = timer(code)
+        except corrx.CorrxError as e:  # a variant this shape cannot use
+            if e.status != corrx.CORRX_EUNSUPPORTED:
+                raise
+            continue
+        if log:
+            log(f"tune {key} code {code:#x}: {times[str(code)]:.3f} ms")
+    best = min(times, key=times.get)
+    cache[key] = {"code": int(best), "ms": times[best], "times": times}
+    return cache[key]
+
+
 def tune_batch(descs, ins, accs, use_cache: bool = True, reps: int = 3, log=None) -> tuple[list[int], dict]:
     """Tile code per array; each array searched alone on its own inputs.
 
@@ -93,20 +147,25 @@ def tune_batch(descs, ins, accs, use_cache: bool = True, reps: int = 3, log=None
     cache = _load_cache(path) if use_cache else {}
     codes, report = [], {}
     for k, d in enumerate(descs):
-        key = _key(d)
-        if key in cache:
-            codes.append(int(cache[key]["code"]))
-            report[key] = cache[key]
-            continue
-        times = {}
-        for code in candidates(d[0]):
-            times[str(code)] = measure([d], [code], [ins[k]], [accs[k]], reps)
-            if log:
-                log(f"tune {key} code {code:#x}: {times[str(code)]:.3f} ms")
-        best = min(times, key=times.get)
-        cache[key] = {"code": int(best), "ms": times[best], "times": times}
+        key = _key(d, "mfma_i8", "batch")
+        if key not in cache:
+            _search(key, cache, candidates(d[0], "batch"),
+                    lambda code: measure([d], [code], [ins[k]], [accs[k]], reps), log)
+        codes.append(int(cache[key]["code"]))
         report[key] = cache[key]
-        codes.append(int(best))
     if use_cache:
         _save_cache(path, cache)
     return codes, report
+
+
+def tune_correlator(desc, inp, acc, use_cache: bool = True, reps: int = 3, log=None) -> tuple[int, dict]:
+    """Tile code for corr_xmac on one array (int8 engine), measured on its
+    input; apply it with Correlator.set_tile.  acc is used as scratch."""
+    path = cache_path()
+    cache = _load_cache(path) if use_cache else {}
+    key = _key(desc, "mfma_i8", "xmac")
+    if key not in cache:
+        _search(key, cache, candidates(desc[0], "xmac"), lambda code: measure_xmac(desc, code, inp, acc, reps), log)
+    if use_cache:
+        _save_cache(path, cache)
+    return int(cache[key]["code"]), cache[key]

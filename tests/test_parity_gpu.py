@@ -455,9 +455,19 @@ def test_random_shapes(cx, oracle_lib, case):
              f"case {case} N={n} F={fc} T={tc} layout={layout} {engine}")
 
 
-@pytest.mark.parametrize("case", range(6))
+def _batch_chunks(cx, unit, n):
+    # chunk lengths the batch kernels have for a unit
+    if unit == cx.CORRX_TILE_UNIT64 or (unit == cx.CORRX_TILE_DEFAULT and n <= 64):
+        return [0, 128, 256]
+    if unit == cx.CORRX_TILE_UNIT128 or (unit == cx.CORRX_TILE_DEFAULT and n <= 128):
+        return [0, 64, 128]
+    return [0, 64]
+
+
+@pytest.mark.parametrize("case", range(8))
 def test_random_batches(cx, oracle_lib, case):
-    # seeded random uneven batches with random valid tile codes
+    # seeded random uneven batches with random valid tile codes (unit, time
+    # splits, chunk length)
     import torch
 
     rng = np.random.default_rng(7000 + case)
@@ -470,7 +480,8 @@ def test_random_batches(cx, oracle_lib, case):
             units.append(cx.CORRX_TILE_UNIT128)
         if n <= 64:
             units.append(cx.CORRX_TILE_UNIT64)
-        codes.append(int(rng.choice(units)) | (int(rng.choice([0, 1, 2, 4])) << 8))
+        unit = int(rng.choice(units))
+        codes.append(cx.tile_code(unit, int(rng.choice([0, 1, 2, 4])), int(rng.choice(_batch_chunks(cx, unit, n)))))
     print(f"random batch {case}: {descs} codes {[hex(c) for c in codes]}", flush=True)
     bufs = [synth.make_input(7100 + 10 * case + k, n, f, t, layout=lay) for k, (n, f, t, lay) in enumerate(descs)]
     b = cx.Batch(descs, tile_cfg=codes)
@@ -481,3 +492,43 @@ def test_random_batches(cx, oracle_lib, case):
     for (n, f, t, lay), x, acc in zip(descs, bufs, accs):
         _compare(acc.cpu().numpy().astype(np.int64), oracle_lib.xmac(x, n, f, t, lay), n, f"batch {case} N={n}")
     b.close()
+
+
+@pytest.mark.parametrize("n", [40, 64, 120, 200, 256, 300])
+def test_set_tile_every_candidate(cx, oracle_lib, n):
+    # corr_xmac under every tile code the tuner may pick (unit, time splits,
+    # chunk length), T ragged for every chunk length, twice in a row
+    import torch
+
+    from paper_1501_05992_amd import tune
+
+    fc, tc = 3, 700
+    buf = synth.make_input(9300 + n, n, fc, tc)
+    want = oracle_lib.xmac(buf, n, fc, tc)
+    x = torch.from_numpy(buf).cuda()
+    codes = tune.candidates(n, "xmac")
+    print(f"N={n}: {len(codes)} codes", flush=True)
+    for code in codes:
+        c = cx.Correlator(n, fc, tc, 0, "mfma_i8")
+        c.set_tile(code)
+        acc = c.new_acc()
+        c.zero(acc)
+        c.xmac(x, acc)
+        c.xmac(x, acc)
+        torch.cuda.synchronize()
+        _compare(acc.cpu().numpy().astype(np.int64), 2 * want, n, f"N={n} code {code:#x}")
+        c.close()
+
+
+def test_set_tile_rejects(cx):
+    c = cx.Correlator(100, 2, 100, 0, "mfma_i8")
+    with pytest.raises(cx.CorrxError) as e:
+        c.set_tile(cx.CORRX_TILE_UNIT64)  # 64-input unit cannot hold 100 inputs
+    assert e.value.status == cx.CORRX_EINVAL
+    with pytest.raises(cx.CorrxError) as e:
+        c.set_tile(cx.tile_code(cx.CORRX_TILE_UNIT256, 0, 128))  # no 128-sample chunk for 256-input units
+    assert e.value.status == cx.CORRX_EUNSUPPORTED
+    with pytest.raises(cx.CorrxError) as e:
+        c.set_tile(1 << 28)
+    assert e.value.status == cx.CORRX_EINVAL
+    c.close()

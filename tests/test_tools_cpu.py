@@ -37,10 +37,19 @@ def test_tuner_candidates_and_cache(tmp_path, monkeypatch):
     from paper_1501_05992_amd import corrx, tune
 
     c64, c256 = tune.candidates(64), tune.candidates(256)
-    assert len(c64) == 3 * len(tune.SPLITS) and len(c256) == len(tune.SPLITS)
+    # batch: 256-input units with the default chunk, 128- and 64-input units with two chunk lengths each
+    assert len(c64) == 5 * len(tune.SPLITS) and len(c256) == len(tune.SPLITS)
     assert all(c & 0xFF == corrx.CORRX_TILE_UNIT256 for c in c256)
     assert {c & 0xFF for c in c64} == {corrx.CORRX_TILE_UNIT64, corrx.CORRX_TILE_UNIT128, corrx.CORRX_TILE_UNIT256}
-    assert {c >> 8 for c in c64} == set(tune.SPLITS)
+    assert {(c >> 8) & 0xFFFF for c in c64} == set(tune.SPLITS)
+    assert {c >> 24 for c in c64} == {0, 2}  # default and 128-sample chunks
+    # corr_xmac: the 64-input unit also has 64- and 256-sample chunks
+    x64 = tune.candidates(64, "xmac")
+    assert len(x64) == 6 * len(tune.SPLITS) and {c >> 24 for c in x64} == {0, 1, 2, 3}
+    assert corrx.tile_code(corrx.CORRX_TILE_UNIT128, 4, 128) == 2 | (4 << 8) | (2 << 24)
+    d = (256, 3072, 10000, 0)
+    assert tune._key(d, "mfma_i8", "xmac", "gfx950") == "gfx950|mfma_i8|xmac|N256|F3072|T10000|L0"
+    assert tune._key(d, "mfma_i8", "xmac", "gfx950") != tune._key(d, "mfma_i8", "batch", "gfx950")
     path = str(tmp_path / "sub" / "tune.json")
     monkeypatch.setenv("CORRX_TUNE_CACHE", path)
     assert tune.cache_path() == path
