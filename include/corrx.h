@@ -328,14 +328,14 @@ typedef struct {
  * CORRX_TILE_* value (the input block a work item stages), time_splits 0 for
  * automatic or the number of time ranges per channel (at most 4096), and
  * chunk the samples a work item stages at a time: 0 for the unit's default,
- * 1, 2, 3 for 64, 128, 256.  The batch kernels have 128 and 256 (default) for
+ * 1, 2, 3 for 64, 128, 256.  The batch kernels have 128 (default) and 256 for
  * 64-input units, 64 (default) and 128 for 128-input units, 64 for 256-input
  * units; other chunks return CORRX_EUNSUPPORTED, malformed codes
  * CORRX_EINVAL.
  */
 enum {
     CORRX_TILE_DEFAULT = 0, /* smallest unit that holds the array's inputs */
-    CORRX_TILE_UNIT64 = 1,  /* 64-input units, two channels per work item (N <= 64) */
+    CORRX_TILE_UNIT64 = 1,  /* 64-input units, one channel per work item (N <= 64) */
     CORRX_TILE_UNIT128 = 2, /* 128-input units, two channels per work item (N <= 128) */
     CORRX_TILE_UNIT256 = 3  /* 256-input diagonal blocks plus cross units (any N) */
 };
@@ -347,8 +347,8 @@ int corr_batch_destroy(corrx_batch_t b);
 int64_t corr_batch_items(corrx_batch_t b);
 
 /* The plan of one array: internal unit kind (0: 256-input blocks, 2: 128-input
- * pairs of channels, 3: 64-input pairs of channels, 4 and 5: the same with
- * 128-sample chunks) and time splits. */
+ * pairs of channels, 3: 64-input channels, 4: 128-input pairs with 128-sample
+ * chunks, 5: 64-input channels with 256-sample chunks) and time splits. */
 int corr_batch_plan(corrx_batch_t b, int array, int *kind, int *splits);
 
 /*

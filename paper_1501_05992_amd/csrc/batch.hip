@@ -46,10 +46,10 @@ bool gfx950(int* dev, int* n_cu) {
 double item_cost(int kind, int n_inputs, int samples) {
   double mfma, bytes;
   switch (kind) {
-    case kUnitDiag64x2:
-    case kUnitDiag64x2K128:
-      mfma = 2.0 * 64 * 64 * samples;
-      bytes = 2.0 * n_inputs * samples;
+    case kUnitDiag64:
+    case kUnitDiag64K256:
+      mfma = 64.0 * 64 * samples;
+      bytes = 1.0 * n_inputs * samples;
       break;
     case kUnitDiag128x2:
     case kUnitDiag128x2K128:
@@ -72,8 +72,8 @@ double item_cost(int kind, int n_inputs, int samples) {
 // if the kernels have no such variant.
 int unit_kind(int unit, int n_inputs, int tc) {
   if (unit == CORRX_TILE_UNIT64 || (unit == CORRX_TILE_DEFAULT && n_inputs <= 64)) {
-    if (tc == 0 || tc == 256) return kUnitDiag64x2;
-    return tc == 128 ? kUnitDiag64x2K128 : -1;
+    if (tc == 0 || tc == 128) return kUnitDiag64;
+    return tc == 256 ? kUnitDiag64K256 : -1;
   }
   if (unit == CORRX_TILE_UNIT128 || (unit == CORRX_TILE_DEFAULT && n_inputs <= 128)) {
     if (tc == 0 || tc == 64) return kUnitDiag128x2;
@@ -81,6 +81,10 @@ int unit_kind(int unit, int n_inputs, int tc) {
   }
   return (tc == 0 || tc == 64) ? kUnitDiag256 : -1;
 }
+
+// Channels one work item covers: the 128-input kinds run two channels side
+// by side in one 512-thread workgroup.
+int items_channels(int kind) { return (kind == kUnitDiag128x2 || kind == kUnitDiag128x2K128) ? 2 : 1; }
 
 int units_of(int kind, int n_inputs) {
   if (kind != kUnitDiag256) return 1;
@@ -133,7 +137,7 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
     const int unit = tile_cfg ? (tile_cfg[a] & 0xFF) : CORRX_TILE_DEFAULT;
     const int kind = unit_kind(unit, d.n_inputs, tile_cfg ? tile_chunk_samples(tile_cfg[a]) : 0);
     b->kind[a] = kind;
-    const int per_item_chan = kind == kUnitDiag256 ? 1 : 2;
+    const int per_item_chan = items_channels(kind);
     const int64_t items = (int64_t)((d.n_chan + per_item_chan - 1) / per_item_chan) * units_of(kind, d.n_inputs);
     total += (double)items * item_cost(kind, d.n_inputs, d.n_time);
   }
@@ -157,7 +161,7 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
     spl = std::min(spl, d.n_time);
     b->splits[a] = spl;
     const int tsplit = (d.n_time + spl - 1) / spl;
-    const int per_item_chan = kind == kUnitDiag256 ? 1 : 2;
+    const int per_item_chan = items_channels(kind);
     const int nb = (d.n_inputs + 255) / 256;
     for (int f = 0; f < d.n_chan; f += per_item_chan)
       for (int u = 0; u < units_of(kind, d.n_inputs); ++u)

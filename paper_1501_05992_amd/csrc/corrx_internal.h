@@ -187,9 +187,9 @@ enum UnitKind {
   kUnitDiag256 = 0,        // one 256-input diagonal block (tile = block index), 64-sample chunks
   kUnitPair = 1,           // one cross unit (tile = pair index: block pair * 2 + half), 64-sample chunks
   kUnitDiag128x2 = 2,      // two 128-input channels (f, f+1) side by side, 64-sample chunks
-  kUnitDiag64x2 = 3,       // two 64-input channels side by side, 256-sample chunks
+  kUnitDiag64 = 3,         // one 64-input channel (256-thread workgroups, two per CU), 128-sample chunks
   kUnitDiag128x2K128 = 4,  // as kUnitDiag128x2 with 128-sample chunks
-  kUnitDiag64x2K128 = 5    // as kUnitDiag64x2 with 128-sample chunks
+  kUnitDiag64K256 = 5      // as kUnitDiag64 with 256-sample chunks
 };
 constexpr int kUnitKinds = 6;
 

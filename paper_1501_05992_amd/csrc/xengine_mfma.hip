@@ -1073,17 +1073,11 @@ int launch_mfma(const Problem& p, int engine, int nsplit, int mode, int tile_cfg
 // switching between kinds would either share one allocation (and spill) or
 // call the units out of line and save their registers on every call.
 
-// The batch's 64-input units take 256-sample chunks: with only two units per
-// compute unit (one workgroup of 512 threads), the longer chunks keep four
-// times as many input bytes in flight per unit as 64-sample chunks.
-constexpr int kBatchTc64 = 256;
-
 template <int KIND>
-constexpr int batch_nb = (KIND == kUnitDiag64x2 || KIND == kUnitDiag64x2K128) ? 64
+constexpr int batch_nb = (KIND == kUnitDiag64 || KIND == kUnitDiag64K256) ? 64
                          : (KIND == kUnitDiag128x2 || KIND == kUnitDiag128x2K128) ? 128 : 256;
 template <int KIND>
-constexpr int batch_tc = KIND == kUnitDiag64x2 ? kBatchTc64
-                         : (KIND == kUnitDiag64x2K128 || KIND == kUnitDiag128x2K128) ? 128 : 64;
+constexpr int batch_tc = KIND == kUnitDiag64K256 ? 256 : (KIND == kUnitDiag64 || KIND == kUnitDiag128x2K128) ? 128 : 64;
 template <int KIND>
 constexpr int batch_lds = KIND == kUnitDiag256 ? DiagGeom<256, 4>::LDS
                           : KIND == kUnitPair  ? CrossGeom::LDS
@@ -1112,9 +1106,31 @@ __device__ inline WorkItem batch_item(const WorkItem* items, int it) {
   return w;
 }
 
+// 64-input units (HBM-bound): 256-thread workgroups, two per compute unit,
+// one channel per item, so that each unit's chunk barriers are its own and
+// one workgroup's loads are in flight while the other computes.
+template <int TC>
+__global__ __launch_bounds__(256, 2) void xmac_batch64_i8(BatchArgs args, const WorkItem* items, int n_items,
+                                                           int* counter, int base_mode) {
+  using G = DiagGeom<64, 2, TC>;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[G::LDS];
+  __shared__ uint32_t s_sy[64], s_sw[64];
+  __shared__ int s_item;
+  (void)args;
+  const Problem* table = (const Problem*)__builtin_amdgcn_kernarg_segment_ptr();
+  int it = batch_fetch(counter, &s_item);
+  while (it < n_items) {
+    const WorkItem w = batch_item(items, it);
+    const Problem p = table[w.array];
+    run_diag<64, 2, true, TC>(p, w.channel, 0, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw,
+                              w.atomic ? (int)kWriteAtomic : base_mode);
+    it = batch_fetch(counter, &s_item);
+  }
+}
+
 // items / n_items: the kind's segment of the work list.  All arrays must be
-// aligned.  The x2 kinds run two units side by side, on channels f and f+1 of
-// the same array (the second writes nothing past the last channel).
+// aligned.  The 128x2 kinds run two units side by side, on channels f and f+1
+// of the same array (the second writes nothing past the last channel).
 template <int KIND>
 __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const WorkItem* items, int n_items,
                                                          int* counter, int base_mode) {
@@ -1175,17 +1191,17 @@ int launch_batch(const BatchArgs& args, const WorkItem* d_items, const BatchSegm
         hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag128x2>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count, ctr,
                            base_mode);
         break;
-      case kUnitDiag64x2:
-        hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag64x2>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count, ctr,
+      case kUnitDiag64:
+        hipLaunchKernelGGL(xmac_batch64_i8<128>, dim3(2 * grid), dim3(256), 0, s, args, it, segs[k].count, ctr,
                            base_mode);
         break;
       case kUnitDiag128x2K128:
         hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag128x2K128>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count,
                            ctr, base_mode);
         break;
-      case kUnitDiag64x2K128:
-        hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag64x2K128>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count,
-                           ctr, base_mode);
+      case kUnitDiag64K256:
+        hipLaunchKernelGGL(xmac_batch64_i8<256>, dim3(2 * grid), dim3(256), 0, s, args, it, segs[k].count, ctr,
+                           base_mode);
         break;
       default:
         return CORRX_EINVAL;

@@ -30,7 +30,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "corrx", "tune.j
 SPLITS = (0, 1, 2, 4, 8)
 
 # K-chunk lengths (samples) each unit has kernels for, first the default.
-BATCH_CHUNKS = {corrx.CORRX_TILE_UNIT64: (0, 128), corrx.CORRX_TILE_UNIT128: (0, 128),
+BATCH_CHUNKS = {corrx.CORRX_TILE_UNIT64: (0, 256), corrx.CORRX_TILE_UNIT128: (0, 128),
                 corrx.CORRX_TILE_UNIT256: (0,)}
 XMAC_CHUNKS = {corrx.CORRX_TILE_UNIT64: (0, 64, 256), corrx.CORRX_TILE_UNIT128: (0, 128),
                corrx.CORRX_TILE_UNIT256: (0,)}

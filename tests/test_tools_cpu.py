@@ -42,7 +42,7 @@ def test_tuner_candidates_and_cache(tmp_path, monkeypatch):
     assert all(c & 0xFF == corrx.CORRX_TILE_UNIT256 for c in c256)
     assert {c & 0xFF for c in c64} == {corrx.CORRX_TILE_UNIT64, corrx.CORRX_TILE_UNIT128, corrx.CORRX_TILE_UNIT256}
     assert {(c >> 8) & 0xFFFF for c in c64} == set(tune.SPLITS)
-    assert {c >> 24 for c in c64} == {0, 2}  # default and 128-sample chunks
+    assert {c >> 24 for c in c64} == {0, 2, 3}  # default, 128- (128-input units), 256-sample chunks (64-input)
     # corr_xmac: the 64-input unit also has 64- and 256-sample chunks
     x64 = tune.candidates(64, "xmac")
     assert len(x64) == 6 * len(tune.SPLITS) and {c >> 24 for c in x64} == {0, 1, 2, 3}
