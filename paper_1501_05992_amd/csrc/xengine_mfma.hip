@@ -576,7 +576,15 @@ __device__ void run_cross(const Problem& p, int f, int I0, int J0, int t0, int t
   // units run in a loop (the persistent kernel), hoisting them out of it would
   // keep them live across the whole unit and exhaust the registers.
   asm volatile("" : "+v"(tid));
-  using S = Stage<CrossGeom::ROWS, 64, CrossGeom::NT, CrossGeom::QROWS, true>;
+  // The unit's coordinates are uniform, but the block decode (a float square
+  // root) leaves them in vector registers: move them to scalar registers so
+  // that the load descriptors and their row arithmetic stay scalar.
+  f = __builtin_amdgcn_readfirstlane(f);
+  I0 = __builtin_amdgcn_readfirstlane(I0);
+  J0 = __builtin_amdgcn_readfirstlane(J0);
+  t0 = __builtin_amdgcn_readfirstlane(t0);
+  t1 = __builtin_amdgcn_readfirstlane(t1);
+  using S = Stage<CrossGeom::ROWS, 64, CrossGeom::NT, CrossGeom::QROWS>;
   static_assert(2 * S::BYTES == CrossGeom::LDS, "two stage buffers");
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave / 4, wc = wave % 4;
