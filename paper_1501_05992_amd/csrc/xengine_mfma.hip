@@ -296,22 +296,38 @@ __device__ inline v4i to_b(v4i a) {
 // Row (within a 32x32 tile) held by accumulator register r of this lane.
 __device__ inline int acc_row(int r, int lane) { return ((r >> 2) << 3) + ((lane >> 5) << 2) + (r & 3); }
 
-// Write UN baselines per thread with one of the write modes; RMW loads are
-// all issued before any store so their latencies overlap.
+// Write UN baselines per thread (element pos[u] of the channel's accumulator
+// out, nb baselines) with one of the write modes.  Store and read-modify-write
+// go through a buffer descriptor over the channel: an element not to be
+// written gets an offset past its end, which the hardware range check drops
+// (stores) or reads as zero (loads), so no branch follows the lane masks.  RMW
+// loads are all issued before any store so their latencies overlap.
 template <int UN>
-__device__ inline void write_out(int2* out, const int64_t (&pos)[UN], const bool (&ok)[UN], const int2 (&val)[UN],
-                                 int mode) {
-  if (mode == kWriteStore) {
+__device__ inline void write_out(int2* out, int64_t nb, const uint32_t (&pos)[UN], const bool (&ok)[UN],
+                                 const int2 (&val)[UN], int mode) {
+  if (mode == kWriteStore || mode == kWriteAdd) {
+    // The channel's base is uniform; reading it from the first lane keeps the
+    // descriptor in scalar registers where the compiler cannot prove that.
+    // n_inputs <= 4096: a channel holds at most 8,390,656 baselines (67 MB).
+    const uint64_t a = reinterpret_cast<uint64_t>(out);
+    int2* base = reinterpret_cast<int2*>(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) << 32) |
+                                         (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a));
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(base, (short)0, __builtin_amdgcn_readfirstlane((int)(8 * nb)), kBufferRsrcWord3);
+    uint32_t off[UN];
 #pragma unroll
-    for (int u = 0; u < UN; ++u)
-      if (ok[u]) out[pos[u]] = val[u];
-  } else if (mode == kWriteAdd) {
-    int2 old[UN];
+    for (int u = 0; u < UN; ++u) off[u] = ok[u] ? 8u * pos[u] : 0x80000000u;
+    if (mode == kWriteAdd) {
+      v2i old[UN];
 #pragma unroll
-    for (int u = 0; u < UN; ++u) old[u] = out[ok[u] ? pos[u] : 0];
+      for (int u = 0; u < UN; ++u) old[u] = __builtin_amdgcn_raw_buffer_load_b64(rs, off[u], 0, 0);
 #pragma unroll
-    for (int u = 0; u < UN; ++u)
-      if (ok[u]) out[pos[u]] = make_int2(old[u].x + val[u].x, old[u].y + val[u].y);
+      for (int u = 0; u < UN; ++u)
+        __builtin_amdgcn_raw_buffer_store_b64(v2i{old[u].x + val[u].x, old[u].y + val[u].y}, rs, off[u], 0, 0);
+    } else {
+#pragma unroll
+      for (int u = 0; u < UN; ++u) __builtin_amdgcn_raw_buffer_store_b64(v2i{val[u].x, val[u].y}, rs, off[u], 0, 0);
+    }
   } else if (mode == kWriteAtomic) {
 #pragma unroll
     for (int u = 0; u < UN; ++u)
@@ -455,7 +471,7 @@ __device__ inline void combine_quadrant(const Problem& p, int f, int ibase, cons
     // diagonal quadrant: passes whose rows all lie above the wave's columns write nothing
     if (diag && r0 + RSTEP * (k0 + UN - 1) < jwave) continue;
     int2 val[UN];
-    int64_t pos[UN];
+    uint32_t pos[UN];
     bool ok[UN];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
@@ -466,9 +482,9 @@ __device__ inline void combine_quadrant(const Problem& p, int f, int ibase, cons
       // 2 Re = G_b[i][j] + G_b[j][i] - e_i - e_j + 256 T,  2 Im = G_b[j][i] - G_b[i][j] + g_i - g_j
       val[u] = make_int2((int)(gij + gji - s_e[li] + cre) >> 1, (int)(gji - gij + s_g[li] - gj) >> 1);
       // n_inputs <= 4096: the offset within the channel fits 32 bits
-      pos[u] = (int64_t)(uint32_t)(((uint32_t)i * (uint32_t)(i + 1) >> 1) + (uint32_t)j);
+      pos[u] = ((uint32_t)i * (uint32_t)(i + 1) >> 1) + (uint32_t)j;
     }
-    write_out<UN>(out, pos, ok, val, mode);
+    write_out<UN>(out, nb, pos, ok, val, mode);
   }
 }
 
@@ -624,46 +640,72 @@ __device__ void run_cross(const Problem& p, int f, int I0, int J0, int t0, int t
                              }
                          });
 
-  // s_sy[k] <- 8 S_k, s_sw[k] stays Sw_k
+  // Correction terms in place: A_k = -8 S_k in s_sy, B_k = 8 S_k - 16 Sw_k in
+  // s_sw, so that Re V = R + A_i + (128 T + A_j) and
+  // Im V = M + B_i + (Sw_j - 8 S_j), with Sw_j = (-A_j - B_j) / 16 exactly.
   __syncthreads();
-  for (int k = tid; k < CrossGeom::ROWS; k += CrossGeom::NT) s_sy[k] = 8u * (s_sy[k] + s_sw[k]);
+  for (int k = tid; k < CrossGeom::ROWS; k += CrossGeom::NT) {
+    const uint32_t s8 = 8u * (s_sy[k] + s_sw[k]);
+    s_sw[k] = s8 - 16u * s_sw[k];
+    s_sy[k] = 0u - s8;
+  }
   __syncthreads();
   const uint32_t tproc = (uint32_t)(nchunks * 64);
   const int64_t nb = tri_index(p.n_inputs, 0);
   int2* out = reinterpret_cast<int2*>(p.acc) + (int64_t)f * nb;
-  // Column terms once per column tile: 128 T - 8 S_j for Re, Sw_j - 8 S_j for Im.
+  // Column terms once per column tile.
   uint32_t cre[2], cim[2];
 #pragma unroll
   for (int z = 0; z < 2; ++z) {
     const int lj = 128 + wc * 64 + 32 * z + (lane & 31);  // stage row of j
-    cre[z] = 128u * tproc - s_sy[lj];
-    cim[z] = s_sw[lj] - s_sy[lj];
+    const uint32_t a = s_sy[lj], b = s_sw[lj];
+    cre[z] = 128u * tproc + a;
+    cim[z] = ((0u - a - b) >> 4) + a;
   }
+  // Accumulator register r of this lane holds row (r >> 2) * 8 + (lane >> 5) * 4
+  // + (r & 3) of its 32 x 32 tile: per (x, rh) eight rows in two runs of four
+  // consecutive rows, whose terms are read with one 16-byte LDS load each and
+  // whose triangle offsets follow from one multiply.
+  const int lrow = wr * 64 + ((lane >> 5) << 2);
+  const uint32_t jl = (uint32_t)(J0 + wc * 64 + (lane & 31));
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int z = 0; z < 2; ++z)
+    for (int rh = 0; rh < 2; ++rh) {
+      uint32_t ra[8], rb[8], rt[8];
+      bool ok[8];
 #pragma unroll
-      for (int rh = 0; rh < 2; ++rh) {
+      for (int g = 0; g < 2; ++g) {
+        const int l0 = lrow + 32 * x + 16 * rh + 8 * g;  // stage row of the run's first row
+        const uint4 a4 = *reinterpret_cast<const uint4*>(s_sy + l0);
+        const uint4 b4 = *reinterpret_cast<const uint4*>(s_sw + l0);
+        const uint32_t i0 = (uint32_t)(I0 + l0);
+        // n_inputs <= 4096: triangle offsets within the channel fit 32 bits
+        uint32_t t = i0 * (i0 + 1) >> 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ra[4 * g + q] = q == 0 ? a4.x : q == 1 ? a4.y : q == 2 ? a4.z : a4.w;
+          rb[4 * g + q] = q == 0 ? b4.x : q == 1 ? b4.y : q == 2 ? b4.z : b4.w;
+          rt[4 * g + q] = t;
+          ok[4 * g + q] = (int)(i0 + q) < p.n_inputs;
+          t += i0 + q + 1;
+        }
+      }
+#pragma unroll
+      for (int z = 0; z < 2; ++z) {
         int2 val[8];
-        int64_t pos[8];
-        bool ok[8];
-        const uint32_t j = (uint32_t)(J0 + wc * 64 + 32 * z + (lane & 31));
+        uint32_t pos[8];
+        const uint32_t j = jl + 32u * z;
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr) {
           const int r = 8 * rh + rr;
-          const int li = wr * 64 + 32 * x + acc_row(r, lane);  // stage row of i
-          const int i = I0 + li;
-          ok[rr] = i < p.n_inputs;
-          const uint32_t s8i = s_sy[li];
-          // Re V = R - 8 S_i - 8 S_j + 128 T,  Im V = M - 16 Sw_i + 8 S_i - 8 S_j + Sw_j
-          val[rr] = make_int2((int)((uint32_t)re[x][z][r] - s8i + cre[z]),
-                              (int)((uint32_t)im[x][z][r] - 16u * s_sw[li] + s8i + cim[z]));
-          // n_inputs <= 4096: the offset within the channel fits 32 bits
-          pos[rr] = (int64_t)(((uint32_t)i * (uint32_t)(i + 1) >> 1) + j);
+          val[rr] = make_int2((int)((uint32_t)re[x][z][r] + ra[rr] + cre[z]),
+                              (int)((uint32_t)im[x][z][r] + rb[rr] + cim[z]));
+          pos[rr] = rt[rr] + j;
         }
-        write_out<8>(out, pos, ok, val, mode);
+        write_out<8>(out, nb, pos, ok, val, mode);
       }
+    }
   __syncthreads();
 }
 
@@ -907,7 +949,7 @@ template <bool ALIGNED>
 __global__ __launch_bounds__(512, 1) void xmac_cross_i8(Problem p, int npair, int nsplit, int tsplit, int mode,
                                                          int* part) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[CrossGeom::LDS];
-  __shared__ uint32_t s_sy[CrossGeom::ROWS], s_sw[CrossGeom::ROWS];
+  __shared__ __attribute__((aligned(16))) uint32_t s_sy[CrossGeom::ROWS], s_sw[CrossGeom::ROWS];
   int u = xcd_remap(blockIdx.x, gridDim.x);
   const int sp = u % nsplit;
   u /= nsplit;
@@ -1143,7 +1185,7 @@ template <int KIND>
 __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const WorkItem* items, int n_items,
                                                          int* counter, int base_mode) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[batch_lds<KIND>];
-  __shared__ uint32_t s_sy[batch_rows<KIND>], s_sw[batch_rows<KIND>];
+  __shared__ __attribute__((aligned(16))) uint32_t s_sy[batch_rows<KIND>], s_sw[batch_rows<KIND>];
   __shared__ int s_item;
   // The problem table is the first kernel argument: read it in place in the
   // kernel-argument segment (taking the address of the by-value parameter
