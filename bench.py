@@ -201,7 +201,7 @@ def main():
                    "algorithmic fp8 ops (8 per complex MAC)",
         "frac": round(xmac_tops / peak, 4),
         "traffic": None,
-        "kernel": "xmac_diag_i8<256,4,true>" if args.engine in ("mfma_i8", "auto") else args.engine,
+        "kernel": "xmac_diag_i8<256,4,true,64>" if args.engine in ("mfma_i8", "auto") else args.engine,
     }
 
     tf = traffic_field(n, fc, tc, args.engine, xmac_ms)
@@ -212,7 +212,7 @@ def main():
     if args.copy_probe:
         copy_probe(torch, dev)
     if not args.no_extras:
-        result["extras"] = extras(corrx, model, synth, torch, dev, x, host, n, fc, tc)
+        result["extras"] = extras(corrx, model, synth, torch, dev, x, host, n, fc, tc, args.stream_integrations)
 
     del acc, dst
     corr.close()
@@ -248,7 +248,7 @@ def time_xmac(corrx, torch, c, x, acc, reps):
     return float(np.median([a.elapsed_time(b) for a, b in evs]))
 
 
-def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
+def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc, stream_integrations=100):
     import oracle
 
     out = {}
@@ -274,7 +274,7 @@ def extras(corrx, model, synth, torch, dev, x, host, n, fc, tc):
     out["pfb_and_output"] = pfb_and_output(corrx, torch, dev, x, n, fc, tc)
     out["fine_pfb"] = fine_pfb(corrx, torch, dev, n, fc // 128)
     out["incoherent_beam"] = incoherent_beam(corrx, synth, torch, dev, oracle, x, host, n, fc, tc)
-    out["streaming"] = streaming(synth, torch)
+    out["streaming"] = streaming(synth, torch, stream_integrations)
     return out
 
 
