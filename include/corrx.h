@@ -28,9 +28,9 @@
  *     are detected before anything is enqueued.  No C++ exception crosses the ABI.
  *   - A handle is used by one host thread and one stream at a time.  Distinct
  *     handles may be used concurrently on different streams.
- *   - Calls other than the *_create / *_destroy ones allocate nothing and
- *     enqueue only kernels on `stream` (no memset, no synchronisation), so they
- *     may be captured into a HIP graph.  The handle's host-side state (samples
+ *   - Calls other than the *_create / *_destroy ones and corr_set_tile (a
+ *     set-up call) allocate nothing and enqueue only kernels on `stream` (no
+ *     memset, no synchronisation), so they may be captured into a HIP graph.  The handle's host-side state (samples
  *     since corr_zero, whether the accumulator was just zeroed, which selects
  *     overwrite or add) advances when a call is made, not when a graph replays
  *     it: capture whole integrations (corr_zero ... corr_dump) so that every
@@ -128,8 +128,9 @@ int corr_set_engine(corrx_t h, int engine);
  * length: 64, 128 or 256 samples for 64-input units, 64 or 128 for 128-input
  * units, 64 for 256-input units (CORRX_EUNSUPPORTED otherwise).
  * Default 0 (built-in choice); other engines ignore it.  A set-up call: it may
- * grow the handle's partial-sum buffer for the requested time splits.
- * tune.py picks codes by measurement.
+ * grow the handle's partial-sum buffer for the requested time splits, so work
+ * queued with the handle must have completed.  tune.py picks codes by
+ * measurement.
  */
 int corr_set_tile(corrx_t h, int tile_cfg);
 /* Engine that corr_xmac will run (AUTO resolved), or a negative status. */
