@@ -36,10 +36,10 @@ KERNEL_SOURCES = ("paper_1501_05992_amd/csrc/xengine_mfma.hip",
                   "paper_1501_05992_amd/csrc/corrx_internal.h",
                   "paper_1501_05992_amd/csrc/api.hip")
 TRAFFIC = {
-    "sources_sha256": "c4cbbac5bff3d3ba3eb6856f061a1e99698c46916fb6c7bd89deafba60388408",
-    "read_bytes": 7864339724,   # FETCH_SIZE 3,840,199 KiB x 2.000
-    "write_bytes": 848075402,   # WRITE_SIZE 828,199 KiB x 1.000
-    "summary": "profiles/xmac_diag_i8_full_band_256x3072x10000_traffic.txt",
+    "sources_sha256": "009622465436d78a0984f198b9cc50341ce636889e0e0c1464ab1f78f5b4f674",
+    "read_bytes": 7864693811,   # FETCH_SIZE 3,840,183 KiB x 2.000
+    "write_bytes": 845068768,   # WRITE_SIZE 825,262 KiB x 1.000
+    "summary": "profiles/xmac_diag_i8_full_band_256x3072x10000_counters.txt",
 }
 
 
