@@ -109,21 +109,22 @@ struct Stage {
   __device__ static int quad(int tid, int k) { return (tid + k * NT) % QUADS; }
 
   // Load the 8 rows x 4 inputs of this thread's items of chunk c.
-  //   ALIGNED (N % 4 == 0, 4-byte aligned buffer): raw buffer loads through a
-  //   descriptor that starts at the chunk's first row and ends at the end of
-  //   the channel's last valid row, so rows past the unit's time range read 0
-  //   in hardware; quads past N use an out-of-range offset.  No branch and no
-  //   select follows a load, so all loads stay in flight.
+  //   ALIGNED (N % 4 == 0, 4-byte aligned buffer): raw buffer loads; quads
+  //   past N use an out-of-range offset and read 0 in hardware.  FULL (every
+  //   row of the chunk lies in the unit's time range): one descriptor for the
+  //   chunk, row r of an item at scalar offset r rows.  Otherwise row r of an
+  //   item uses a descriptor whose base is advanced by r rows and whose range
+  //   ends at the channel's last valid row, so rows past the unit's time
+  //   range read 0 in hardware.  Either way the per-lane offset is the same
+  //   for all 8 rows of the item, and no branch and no select follows a
+  //   load, so all loads stay in flight.
   //   Otherwise: byte loads (slow path).
-  template <bool ALIGNED>
+  template <bool ALIGNED, bool FULL = false>
   __device__ static void load(const Problem& p, const Map& m, int f, int t0, int t1, int c, int64_t stride, int tid,
                               uint32_t (&ld)[ITER][8]) {
     const int tb = t0 + c * TC;
     if constexpr (ALIGNED) {
-      // Row r of an item uses a descriptor whose base is advanced by r rows
-      // (scalar arithmetic) and whose range ends at the channel's last valid
-      // row, so the per-lane offset is the same for all 8 rows of the item.
-      const int rows = min(t1 - tb, TC);
+      const int rows = FULL ? TC : min(t1 - tb, TC);
       // TC rows of a channel span less than 2^31 bytes (checked on the host),
       // so the range arithmetic stays in 32-bit scalar registers.
       const int stride32 = (int)stride;
@@ -136,6 +137,24 @@ struct Stage {
         const int q = item % QUADS, g = item / QUADS;
         const int i = m.input(q);
         off[k] = (i < p.n_inputs && has_item(tid, k)) ? (uint32_t)(8 * g * stride + i) : 0x80000000u;
+      }
+      if constexpr (FULL) {
+        const uint8_t* rb = base;
+        int nr = nrec0;
+        if constexpr (SCALAR_RSRC) {
+          nr = __builtin_amdgcn_readfirstlane(nr);
+          const uint64_t a = reinterpret_cast<uint64_t>(rb);
+          rb = reinterpret_cast<const uint8_t*>(
+              ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) << 32) |
+              (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a));
+        }
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(rb), (short)0, nr, kBufferRsrcWord3);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+          for (int k = 0; k < ITER; ++k) ld[k][r] = __builtin_amdgcn_raw_buffer_load_b32(rs, off[k], r * stride32, 0);
+        return;
       }
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -361,8 +380,9 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
   }
   __syncthreads();
 
-  auto step = [&](int c, auto more1, auto more2) {
-    constexpr bool M1 = decltype(more1)::value, M2 = decltype(more2)::value;
+  // full2: chunk c + 2 lies wholly in [t0, t1)
+  auto step = [&](int c, auto more1, auto more2, auto full2) {
+    constexpr bool M1 = decltype(more1)::value, M2 = decltype(more2)::value, F2 = decltype(full2)::value;
     const uint8_t* st = lds + (c & 1) * S::BYTES;
     uint8_t* nst = lds + ((c + 1) & 1) * S::BYTES;
     uint32_t bad = 0;
@@ -379,7 +399,7 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
       }
       if constexpr (M2) {
         if (ks == S::LOAD_PHASE * S::KSTEPS / 4)
-          S::template load<ALIGNED>(p, m, f, t0, t1, c + 2, stride, tid, ld);
+          S::template load<ALIGNED, F2>(p, m, f, t0, t1, c + 2, stride, tid, ld);
       }
     }
     if constexpr (M1 && !S::FP8) {
@@ -391,12 +411,17 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
   using T_ = std::true_type;
   using F_ = std::false_type;
   int c = 0;
-  for (; c + 2 < nchunks; ++c) step(c, T_{}, T_{});
-  if (c + 1 < nchunks) {
-    step(c, T_{}, F_{});
+  // every chunk but the last is whole
+  for (; c + 3 < nchunks; ++c) step(c, T_{}, T_{}, T_{});
+  if (c + 2 < nchunks) {
+    step(c, T_{}, T_{}, F_{});
     ++c;
   }
-  if (c < nchunks) step(c, F_{}, F_{});
+  if (c + 1 < nchunks) {
+    step(c, T_{}, F_{}, F_{});
+    ++c;
+  }
+  if (c < nchunks) step(c, F_{}, F_{}, F_{});
   if constexpr (!S::FP8) S::flush(bu, bw, s_su, s_sw, tid);
 }
 
@@ -741,10 +766,10 @@ struct StageF8 {
   static_assert(ITER == 1, "one unpack item per thread");
   using Map = typename L::Map;
 
-  template <bool ALIGNED>
+  template <bool ALIGNED, bool FULL = false>
   __device__ static void load(const Problem& p, const Map& m, int f, int t0, int t1, int c, int64_t stride, int tid,
                               uint32_t (&ld)[ITER][8]) {
-    L::template load<ALIGNED>(p, m, f, t0, t1, c, stride, tid, ld);
+    L::template load<ALIGNED, FULL>(p, m, f, t0, t1, c, stride, tid, ld);
   }
 
   // Two samples (bytes 2h, 2h+1 of the raw word x) of one input -> one A
