@@ -86,9 +86,10 @@ __device__ inline uint32_t invalid_flags(uint32_t y) {
 __device__ inline uint32_t invalid_flags_raw(uint32_t x, uint32_t k) { return ((x ^ 0x88888888u) + k) & x; }
 
 // A constant the compiler must hold in a vector register: the empty asm
-// statement emits no instruction, it only hides the value.
+// statement emits no instruction, it only hides the value.  It is not
+// volatile, so the compiler may hoist it out of loops.
 __device__ inline uint32_t vconst(uint32_t c) {
-  asm volatile("" : "+v"(c));
+  asm("" : "+v"(c));
   return c;
 }
 

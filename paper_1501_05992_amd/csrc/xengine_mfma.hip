@@ -78,6 +78,14 @@ struct Stage {
   static constexpr int ITEMS = QUADS * GROUPS;       // unpack items (8 rows x 4 inputs)
   static constexpr int ITER = (ITEMS + NT - 1) / NT;
   static constexpr bool EXACT = ITEMS % NT == 0;
+  // Split item order (cross units): item slot 0 of every thread holds one
+  // item of the quads without the Q form, slot 1 of the first threads one
+  // item of the Q quads.  Each slot is then wholly Q or wholly not, and slot
+  // 1 exists for whole waves, so neither test needs a per-lane branch.
+  static constexpr int QQUADS = QROWS / 4;
+  static constexpr int PQUADS = QUADS - QQUADS;
+  static constexpr bool SPLIT =
+      QROWS > 0 && PQUADS * GROUPS == NT && QQUADS * GROUPS <= NT && (QQUADS * GROUPS) % 64 == 0;
   // When NT is a multiple of QUADS, all items of a thread cover the same
   // four inputs and share one set of per-input sums.
   static constexpr bool SHARED_Q = NT % QUADS == 0;
@@ -105,8 +113,24 @@ struct Stage {
   // granule of consecutive rows) and unpack stores (one granule of every
   // fourth row) are free of bank conflicts.
   __device__ static int swz(int row) { return (row ^ (row >> 2)) & (GRAN - 1); }
-  __device__ static bool has_item(int tid, int k) { return EXACT || tid + k * NT < ITEMS; }
-  __device__ static int quad(int tid, int k) { return (tid + k * NT) % QUADS; }
+  __device__ static bool has_item(int tid, int k) {
+    if constexpr (SPLIT) return k == 0 || __builtin_amdgcn_readfirstlane(tid) < QQUADS * GROUPS;
+    return EXACT || tid + k * NT < ITEMS;
+  }
+  // Stage quad and 8-row group of item slot k of thread tid.
+  __device__ static int quad(int tid, int k) {
+    if constexpr (SPLIT) return k == 0 ? QQUADS + tid % PQUADS : tid % QQUADS;
+    return (tid + k * NT) % QUADS;
+  }
+  __device__ static int group(int tid, int k) {
+    if constexpr (SPLIT) return k == 0 ? tid / PQUADS : tid / QQUADS;
+    return (tid + k * NT) / QUADS;
+  }
+  // Whether slot k's rows also take the Q form.
+  __device__ static bool q_rows(int tid, int k) {
+    if constexpr (SPLIT) return k == 1;
+    return 4 * quad(tid, k) < QROWS;
+  }
 
   // Load the 8 rows x 4 inputs of this thread's items of chunk c.
   //   ALIGNED (N % 4 == 0, 4-byte aligned buffer): raw buffer loads; quads
@@ -129,13 +153,13 @@ struct Stage {
       // so the range arithmetic stays in 32-bit scalar registers.
       const int stride32 = (int)stride;
       const int nrec0 = (rows - 1) * stride32 + p.n_inputs;
-      const uint8_t* base = p.in + row_offset(p, f, tb);
+      // the unit's first row (loop-invariant) advanced by c chunks of TC rows
+      const uint8_t* base = p.in + row_offset(p, f, t0) + (int64_t)c * (TC * stride32);
       uint32_t off[ITER];
 #pragma unroll
       for (int k = 0; k < ITER; ++k) {
-        const int item = tid + k * NT;
-        const int q = item % QUADS, g = item / QUADS;
-        const int i = m.input(q);
+        const int g = group(tid, k);
+        const int i = m.input(quad(tid, k));
         off[k] = (i < p.n_inputs && has_item(tid, k)) ? (uint32_t)(8 * g * stride + i) : 0x80000000u;
       }
       if constexpr (FULL) {
@@ -175,9 +199,8 @@ struct Stage {
     } else {
 #pragma unroll
       for (int k = 0; k < ITER; ++k) {
-        const int item = tid + k * NT;
-        const int q = item % QUADS, g = item / QUADS;
-        const int i = m.input(q);
+        const int g = group(tid, k);
+        const int i = m.input(quad(tid, k));
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           const int t = tb + 8 * g + r;
@@ -219,8 +242,7 @@ struct Stage {
 
   __device__ static void store_input(const uint32_t (&x)[8], uint8_t* st, int k, int c, uint32_t (&bu)[SUMS][4],
                                      uint32_t (&bw)[SUMS][4], int tid) {
-    const int item = tid + k * NT;
-    const int q = item % QUADS, g = item / QUADS;
+    const int q = quad(tid, k), g = group(tid, k);
     const int row = 4 * q + c;
     const uint32_t xa = x[2 * c], xb = x[2 * c + 1];
     const uint32_t ra = bu4(xa), ia = bw4(xa), rb = bu4(xb), ib = bw4(xb);
@@ -230,7 +252,7 @@ struct Stage {
     const int off = row * ROWB + ((g ^ swz(row)) << 4);
     *reinterpret_cast<v4i*>(st + off) = v4i{(int)ra, (int)ia, (int)rb, (int)ib};
     if constexpr (QROWS > 0) {
-      if (row < QROWS)
+      if (q_rows(tid, k))
         *reinterpret_cast<v4i*>(st + PBYTES + off) =
             v4i{(int)bw4(xa), (int)(ra ^ 0x0F0F0F0Fu), (int)bw4(xb), (int)(rb ^ 0x0F0F0F0Fu)};
     }
