@@ -402,11 +402,15 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
   }
   __syncthreads();
 
-  // full2: chunk c + 2 lies wholly in [t0, t1)
-  auto step = [&](int c, auto more1, auto more2, auto full2) {
+  // full2: chunk c + 2 lies wholly in [t0, t1).  parity: c & 1 when known
+  // at compile time (the stage buffers' offset then folds into the LDS
+  // instructions' immediate offsets), else -1.
+  auto step = [&](int c, auto more1, auto more2, auto full2, auto parity) {
     constexpr bool M1 = decltype(more1)::value, M2 = decltype(more2)::value, F2 = decltype(full2)::value;
-    const uint8_t* st = lds + (c & 1) * S::BYTES;
-    uint8_t* nst = lds + ((c + 1) & 1) * S::BYTES;
+    constexpr int P = decltype(parity)::value;
+    const int cur = P < 0 ? (c & 1) : P;
+    const uint8_t* st = lds + cur * S::BYTES;
+    uint8_t* nst = lds + (cur ^ 1) * S::BYTES;
     uint32_t bad = 0;
     uint32_t x[8];
 #pragma unroll
@@ -432,18 +436,28 @@ __device__ inline void run_chunks(const Problem& p, const typename S::Map& m, in
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
+  using P0 = std::integral_constant<int, 0>;
+  using P1 = std::integral_constant<int, 1>;
+  using PX = std::integral_constant<int, -1>;
   int c = 0;
-  // every chunk but the last is whole
-  for (; c + 3 < nchunks; ++c) step(c, T_{}, T_{}, T_{});
+  // every chunk but the last is whole; the main loop takes two per pass
+  for (; c + 4 < nchunks; c += 2) {
+    step(c, T_{}, T_{}, T_{}, P0{});
+    step(c + 1, T_{}, T_{}, T_{}, P1{});
+  }
+  if (c + 3 < nchunks) {
+    step(c, T_{}, T_{}, T_{}, PX{});
+    ++c;
+  }
   if (c + 2 < nchunks) {
-    step(c, T_{}, T_{}, F_{});
+    step(c, T_{}, T_{}, F_{}, PX{});
     ++c;
   }
   if (c + 1 < nchunks) {
-    step(c, T_{}, F_{}, F_{});
+    step(c, T_{}, F_{}, F_{}, PX{});
     ++c;
   }
-  if (c < nchunks) step(c, F_{}, F_{}, F_{});
+  if (c < nchunks) step(c, F_{}, F_{}, F_{}, PX{});
   if constexpr (!S::FP8) S::flush(bu, bw, s_su, s_sw, tid);
 }
 
