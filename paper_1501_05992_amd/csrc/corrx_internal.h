@@ -85,6 +85,13 @@ __device__ inline uint32_t invalid_flags(uint32_t y) {
 // second constant in a vector register the compiler forms one v_xad_u32.
 __device__ inline uint32_t invalid_flags_raw(uint32_t x, uint32_t k) { return ((x ^ 0x88888888u) + k) & x; }
 
+// acc | invalid_flags_raw(x, k) with the AND and the OR in one v_bitop3_b32:
+// table 0xEC is (S0 & S2) | S1, the same function whichever of S0 and S2 the
+// hardware takes as the table's high index bit.
+__device__ inline uint32_t or_invalid_flags_raw(uint32_t x, uint32_t k, uint32_t acc) {
+  return __builtin_amdgcn_bitop3_b32((x ^ 0x88888888u) + k, acc, x, 0xEC);
+}
+
 // A constant the compiler must hold in a vector register: the empty asm
 // statement emits no instruction, it only hides the value.  It is not
 // volatile, so the compiler may hoist it out of loops.

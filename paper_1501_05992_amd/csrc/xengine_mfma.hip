@@ -236,8 +236,10 @@ struct Stage {
     x[4 + tq] = e2;
     x[6 + tq] = e3;
     const uint32_t kc = vconst(0xEEEEEEEFu);
-    bad |= invalid_flags_raw(e0, kc) | invalid_flags_raw(e1, kc) | invalid_flags_raw(e2, kc) |
-           invalid_flags_raw(e3, kc);
+    bad = or_invalid_flags_raw(e0, kc, bad);
+    bad = or_invalid_flags_raw(e1, kc, bad);
+    bad = or_invalid_flags_raw(e2, kc, bad);
+    bad = or_invalid_flags_raw(e3, kc, bad);
   }
 
   __device__ static void store_input(const uint32_t (&x)[8], uint8_t* st, int k, int c, uint32_t (&bu)[SUMS][4],
