@@ -20,7 +20,7 @@ struct corrx_batch {
   int grid;
   int n_items;
   WorkItem* d_items;
-  int* d_counter;  // one queue counter per segment
+  int* d_counter;  // the queue counters of every segment (kBatchCounters)
   int n_segs;
   BatchSegment segs[kMaxSegments];
   void* zeroed[kMaxBatch];  // accumulators set to zero by corr_batch_zero and not written since
@@ -209,7 +209,7 @@ int corr_batch_create(const corrx_desc* descs, int n, int engine, const int* til
   }
   b->n_items = (int)items.size();
   if (hipMalloc(&b->d_items, sizeof(WorkItem) * items.size()) != hipSuccess ||
-      hipMalloc(&b->d_counter, sizeof(int) * kMaxSegments) != hipSuccess) {
+      hipMalloc(&b->d_counter, sizeof(int) * kBatchCounters) != hipSuccess) {
     (void)hipFree(b->d_items);
     delete b;
     return CORRX_ENOMEM;

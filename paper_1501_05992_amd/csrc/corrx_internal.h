@@ -225,9 +225,10 @@ struct BatchSegment {
   int count;
 };
 constexpr int kMaxSegments = kUnitKinds;  // one per unit kind
+constexpr int kBatchCounters = kMaxSegments * 8;  // eight queues (one per XCD) per segment
 
 // One persistent launch per segment (after one launch that resets the
-// segments' counters).  base_mode: kWriteStore (all accumulators freshly
+// segments' queue counters: kBatchCounters ints at d_counters).  base_mode: kWriteStore (all accumulators freshly
 // zeroed) or kWriteAdd; items with time splits always add atomically.
 int launch_batch(const BatchArgs& args, const WorkItem* d_items, const BatchSegment* segs, int n_segs, int* d_counters,
                  int grid, int base_mode, hipStream_t s);

@@ -1198,9 +1198,32 @@ constexpr int batch_lds = KIND == kUnitDiag256 ? DiagGeom<256, 4>::LDS
 template <int KIND>
 constexpr int batch_rows = KIND == kUnitPair ? CrossGeom::ROWS : 256;
 
-// Next work item of the persistent kernel (same value in every thread).
-__device__ inline int batch_fetch(int* counter, int* s_item) {
-  if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
+// Work queues per XCD.  Queue x holds the x-th eighth of a segment's items
+// (a contiguous run: neighbouring channels, and the units of one channel).
+// Workgroups are dealt to the 8 XCDs round-robin by id, so workgroup b takes
+// items from queue b % 8 first, then from the others in turn once that one
+// is empty.  Items that share input rows then run on one XCD, at about the
+// same time, and share its L2 -- as the unit order of the standalone grids
+// does.  Any queue order is correct: every item is taken exactly once.
+constexpr int kQueues = 8;
+
+// Next work item of the persistent kernel (same value in every thread), or
+// n_items once every queue is empty.  ctr: kQueues counters, zero at launch.
+__device__ inline int batch_fetch(int* ctr, int n_items, int* s_item) {
+  if (threadIdx.x == 0) {
+    const int x0 = (int)(blockIdx.x % kQueues);
+    int it = n_items;
+    for (int d = 0; d < kQueues; ++d) {
+      const int x = (x0 + d) % kQueues;
+      const int b = (int)((int64_t)x * n_items / kQueues), e = (int)((int64_t)(x + 1) * n_items / kQueues);
+      const int k = atomicAdd(&ctr[x], 1);
+      if (k < e - b) {
+        it = b + k;
+        break;
+      }
+    }
+    *s_item = it;
+  }
   __syncthreads();
   const int it = *s_item;
   __syncthreads();
@@ -1231,13 +1254,13 @@ __global__ __launch_bounds__(256, 2) void xmac_batch64_i8(BatchArgs args, const 
   __shared__ int s_item;
   (void)args;
   const Problem* table = (const Problem*)__builtin_amdgcn_kernarg_segment_ptr();
-  int it = batch_fetch(counter, &s_item);
+  int it = batch_fetch(counter, n_items, &s_item);
   while (it < n_items) {
     const WorkItem w = batch_item(items, it);
     const Problem p = table[w.array];
     run_diag<64, 2, true, TC>(p, w.channel, 0, w.t0, w.t1, threadIdx.x, lds, s_sy, s_sw,
                               w.atomic ? (int)kWriteAtomic : base_mode);
-    it = batch_fetch(counter, &s_item);
+    it = batch_fetch(counter, n_items, &s_item);
   }
 }
 
@@ -1255,7 +1278,7 @@ __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const Wo
   // would copy it to private memory).
   (void)args;
   const Problem* table = (const Problem*)__builtin_amdgcn_kernarg_segment_ptr();
-  int it = batch_fetch(counter, &s_item);
+  int it = batch_fetch(counter, n_items, &s_item);
   while (it < n_items) {
     const WorkItem w = batch_item(items, it);
     const Problem p = table[w.array];
@@ -1275,7 +1298,7 @@ __global__ __launch_bounds__(512, 1) void xmac_batch_i8(BatchArgs args, const Wo
                                 lds + g * DiagGeom<NB, 2, TC>::LDS, s_sy + NB * g, s_sw + NB * g,
                                 f < p.n_chan ? mode : (int)kWriteNone);
     }
-    it = batch_fetch(counter, &s_item);
+    it = batch_fetch(counter, n_items, &s_item);
   }
 }
 
@@ -1287,10 +1310,11 @@ int launch_batch(const BatchArgs& args, const WorkItem* d_items, const BatchSegm
                  int grid, int base_mode, hipStream_t s) {
   if (n_segs < 0 || n_segs > kMaxSegments) return CORRX_EINVAL;
   if (n_segs == 0) return CORRX_OK;  // no work items
-  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(kMaxSegments), 0, s, d_counters, n_segs);
+  static_assert(kBatchCounters == kMaxSegments * kQueues, "queue counters per segment");
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(kBatchCounters), 0, s, d_counters, n_segs * kQueues);
   for (int k = 0; k < n_segs; ++k) {
     const WorkItem* it = d_items + segs[k].begin;
-    int* ctr = d_counters + k;
+    int* ctr = d_counters + k * kQueues;
     switch (segs[k].kind) {
       case kUnitDiag256:
         hipLaunchKernelGGL(xmac_batch_i8<kUnitDiag256>, dim3(grid), dim3(512), 0, s, args, it, segs[k].count, ctr,
