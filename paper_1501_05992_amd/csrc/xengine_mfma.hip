@@ -1055,10 +1055,13 @@ __global__ __launch_bounds__(512, 1) void xmac_diag_f8(Problem p, int nsplit, in
   run_diag_f8<ALIGNED>(p, f, 0, t0, t1, threadIdx.x, lds, s_sy, s_sw, nsplit > 1 ? (int)kWriteAtomic : mode);
 }
 
+// The raw-buffer loads need N % 4 == 0, a 4-byte aligned input and a chunk of
+// rows (up to 256, the longest chunk) spanning less than 2^31 bytes, so that
+// their ranges and offsets stay in 32 bits.
 static bool aligned_problem(const Problem& p) {
   const int64_t stride = p.layout == CORRX_LAYOUT_TFI ? (int64_t)p.n_chan * p.n_inputs : p.n_inputs;
   return (p.n_inputs % 4 == 0) && ((reinterpret_cast<uintptr_t>(p.in) & 3) == 0) &&
-         128 * stride + p.n_inputs < 0x7FFFFFFF;
+         256 * stride + p.n_inputs < 0x7FFFFFFF;
 }
 
 template <int NB, int WC, int TC>
