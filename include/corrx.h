@@ -316,14 +316,15 @@ typedef struct {
 
 /*
  * Plan a batch of n arrays (1 <= n <= 64) of uneven shapes, run by one
- * persistent launch: one workgroup per compute unit pulls work items (array,
- * channel, tile, time range) from a device queue, longest first.  The paper's
+ * persistent launch per kind of work unit present: one workgroup per compute
+ * unit pulls work items (array, channel, tile, time range) from device
+ * queues (eight per kind, one per XCD), longest first.  The paper's
  * correlator fixes the number of stations, channels and samples when it is
  * compiled (Sec. 3.3.3, footnote on compile-time parameters); here every
  * array of the batch has its own run-time shape.  Each array needs
  * n_inputs % 4 == 0 and 4-byte aligned input (else CORRX_EUNSUPPORTED).
  * engine: CORRX_ENGINE_MFMA_I8 or AUTO.  Allocates the device work list and
- * the queue counter (freed by corr_batch_destroy).
+ * its queue counters (freed by corr_batch_destroy).
  * tile_cfg: NULL (built-in choice) or one code per array, chosen by the
  * autotuner: (unit) | (time_splits << 8) | (chunk << 24), with unit a
  * CORRX_TILE_* value (the input block a work item stages), time_splits 0 for
@@ -365,7 +366,7 @@ int corr_batch_zero(corrx_batch_t b, void *const *accs, void *stream);
  * For every array a: accs[a] += V(ins[a]) (Sec. 2 eq. (3), Sec. 3.4, as
  * corr_xmac).  ins and accs are HOST arrays of n DEVICE pointers (same
  * meaning as for corr_xmac, one per array; accs 8-byte aligned).  One
- * persistent launch (plus a one-thread queue reset) on `stream`.  The handle
+ * persistent launch per unit kind (plus a one-block queue reset) on `stream`.  The handle
  * counts each array's samples since corr_batch_zero; a call that would take
  * any array past 21,913,098 samples (the int32 bound, |Re|, |Im| <= 98 per
  * sample) returns CORRX_EOVERFLOW and enqueues nothing.
