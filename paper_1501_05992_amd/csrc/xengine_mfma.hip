@@ -584,19 +584,35 @@ __device__ void run_diag(const Problem& p, int f, int ibase, int t0, int t1, int
   const int half = lane >> 5;
   const int rrow = wr * G::TM + (lane & 31), crow = wc * G::TN + (lane & 31);
   const typename S::Map m{ibase, NB / 4, ibase};
+  // fragments of K-steps ks (slot ks & 1) and ks + 1 (the other slot): the
+  // next K-step's reads are issued before this one's MFMAs
+  v4i fa[2][G::FM], fb[2][G::FN];
   run_chunks<S, ALIGNED>(p, m, f, t0, t1, stride, tid, lds, s_sy, s_sw, nchunks,
                          [&](const uint8_t* st, int ks) {
-                           v4i a[G::FM], b[G::FN];
+                           const int cb = ks & 1, nb = cb ^ 1;
+                           if (ks == 0) {
 #pragma unroll
-                           for (int x = 0; x < G::FM; ++x) a[x] = S::read_frag(st, rrow + 32 * x, 2 * ks + half);
+                             for (int x = 0; x < G::FM; ++x) fa[cb][x] = S::read_frag(st, rrow + 32 * x, half);
 #pragma unroll
-                           for (int x = 0; x < G::FN; ++x)
-                             b[x] = to_b(S::read_frag(st, crow + 32 * x, 2 * ks + half));
+                             for (int x = 0; x < G::FN; ++x) fb[cb][x] = to_b(S::read_frag(st, crow + 32 * x, half));
+                           }
+                           if (ks + 1 < S::KSTEPS) {
+#pragma unroll
+                             for (int x = 0; x < G::FM; ++x)
+                               fa[nb][x] = S::read_frag(st, rrow + 32 * x, 2 * (ks + 1) + half);
+#pragma unroll
+                             for (int x = 0; x < G::FN; ++x)
+                               fb[nb][x] = S::read_frag(st, crow + 32 * x, 2 * (ks + 1) + half);
+                           }
 #pragma unroll
                            for (int x = 0; x < G::FM; ++x)
 #pragma unroll
                              for (int z = 0; z < G::FN; ++z)
-                               acc[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[x], b[z], acc[x][z], 0, 0, 0);
+                               acc[x][z] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[cb][x], fb[cb][z], acc[x][z], 0, 0, 0);
+                           if (ks + 1 < S::KSTEPS) {
+#pragma unroll
+                             for (int x = 0; x < G::FN; ++x) fb[nb][x] = to_b(fb[nb][x]);
+                           }
                          });
 
   // correction terms in place: e_k = 16 Su_k + 31 Sw_k, g_k = 16 Su_k - Sw_k
