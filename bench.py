@@ -36,9 +36,9 @@ KERNEL_SOURCES = ("paper_1501_05992_amd/csrc/xengine_mfma.hip",
                   "paper_1501_05992_amd/csrc/corrx_internal.h",
                   "paper_1501_05992_amd/csrc/api.hip")
 TRAFFIC = {
-    "sources_sha256": "66685fc2256778c64adb1350e5f328c5f06754dc50ef9a5114ee7f921fa3270c",
-    "read_bytes": 7864784051,   # FETCH_SIZE 3,840,227 KiB x 2.000
-    "write_bytes": 844692038,   # WRITE_SIZE 824,895 KiB x 1.000
+    "sources_sha256": "8a119165a1bb5fa6861bbff44e152699d60968bee6c8624a7b86a197387a6371",
+    "read_bytes": 7864783155,   # FETCH_SIZE 3,840,226 KiB x 2.000
+    "write_bytes": 844381530,   # WRITE_SIZE 824,591 KiB x 1.000
     "summary": "profiles/xmac_diag_i8_full_band_256x3072x10000_counters.txt",
 }
 
